@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the decomposed-time tomography hot path on one MI355X.
+
+One step = one iteration of the adapted Chambolle-Pock loop (Sec. 3, Fig. 2)
+on the plain FP32 workload: 512 x 512 x 128 volume, K = 16 cosine basis
+functions, 1800 projections over 10 half-turns (180 per half-turn), 512
+detector bins, 10 time frames; synthetic data from 40 moving ellipsoids and
+a growing sphere with 1% Gaussian noise.  A step runs R_T with the h1 prox,
+the 4D gradient with the shrink, R_T*, the divergence with the primal update
+and extrapolation, and the FP64 monitors (residual, TV, relative change).
+
+value = delivered R_T + R_T* ray-samples per second / 1e9 (2 Ntheta Nz Ns N
+per iteration), inputs resident in HBM.  Prints one JSON line on stdout.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+  python bench.py --copy-calib     # plain copy kernel for counter calibration
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "R_T+R_T* Gray-samples/s, solver iters/s; served p50/p99 latency vs plain"
+PEAK_HBM = 8.0e12                               # B/s, MI355X HBM3E
+# FP32 FMA issue without packed math: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9           # 78.6 TFLOP/s
+KERNELS = ("k_project", "k_contract", "k_fold", "k_backproject", "k_grad_shrink",
+           "k_div_update")
+SOURCES = {"k_project": "proj_pf.hip", "k_contract": "proj_pf.hip", "k_fold": "proj_pf.hip",
+           "k_backproject": "proj_pf.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def c2_geom():
+    from paper_1809_09725_amd import rt4d
+    return rt4d.Geom(N=512, Nz=128, Ns=512, Ntheta=1800, Npi=10, K=16, Nt=10)
+
+
+def algorithmic(kernel: str, G) -> tuple[str, float]:
+    """(bound, algorithmic flops or bytes of one launch)."""
+    n0 = G.Ntheta // G.Npi
+    nvox = G.Nz * G.N * G.N
+    if kernel == "k_project":       # 2 taps x 1 FMA per channel-sample on every ray step
+        return "alu", 4.0 * G.K * n0 * G.Nz * G.Ns * G.N
+    if kernel == "k_backproject":   # 2 taps x 1 FMA per channel per voxel and class
+        return "alu", 4.0 * G.K * n0 * G.Nz * G.N * G.N
+    if kernel == "k_grad_shrink":   # read f~, read + write h2
+        return "hbm", nvox * (4.0 * G.K + 2 * 16.0 * G.Nt)
+    if kernel == "k_div_update":    # read h2, f, R*h1; write f, f~
+        return "hbm", nvox * (16.0 * G.Nt + 4 * 4.0 * G.K)
+    if kernel == "k_contract":      # read P, g, h1; write h1
+        return "hbm", n0 * G.Nz * G.Ns * 4.0 * G.K + G.Ntheta * G.Nz * G.Ns * 12.0
+    if kernel == "k_fold":          # read g, write g~
+        return "hbm", G.Ntheta * G.Nz * G.Ns * 4.0 + n0 * G.Nz * G.Ns * 4.0 * G.K
+    raise KeyError(kernel)
+
+
+def source_sha(kernel: str) -> str:
+    p = os.path.join(ROOT, "paper_1809_09725_amd", "csrc", SOURCES[kernel])
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha") != source_sha(kernel):
+            return None
+        scale = float(kv["copy_scale"])
+        return (float(kv["fetch_kib_per_dispatch"]) + float(kv["write_kib_per_dispatch"])) * 1024 * scale
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(G, g_slice, seed: int) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample: R_T and R_T* over
+    all 1800 projections of one slice (slices are independent under
+    parallel-beam geometry)."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1809_09725_amd import inputs
+    og = O.Geom(N=G.N, Nz=1, Ns=G.Ns, Ntheta=G.Ntheta, Npi=G.Npi, K=G.K, Nt=G.Nt)
+    f = inputs.uniform((1, G.N, G.N, G.K), seed)
+    O.build()
+    t0 = time.perf_counter()
+    O.forward(og, f)
+    t1 = time.perf_counter()
+    O.adjoint(og, np.asarray(g_slice, np.float64))
+    t2 = time.perf_counter()
+    samples = 2.0 * G.Ntheta * 1 * G.Ns * G.N
+    return {"value": samples / (t2 - t0) / 1e9, "unit": "Gray-samples/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one slice (z=0 of {G.Nz}) of the workload: R_T then R_T* over all "
+                      f"{G.Ntheta} projections, direct FP64 route; forward {t1 - t0:.2f} s, "
+                      f"adjoint {t2 - t1:.2f} s"}
+
+
+def copy_calib():
+    import torch
+    n = 1 << 28                      # 1 GiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_bytes_per_direction": 4 * n, "dispatches": 3}))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(the z-slab sharding across GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        return 2
+    if args.copy_calib:
+        copy_calib()
+        return 0
+
+    import torch
+
+    from paper_1809_09725_amd import inputs, rt4d
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    G = c2_geom()
+    log(f"workload {G}")
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 40, seed=2, axis_range=(G.N / 64, G.N / 16),
+                             z_axis_range=(G.Nz / 16, G.Nz / 4), rho_range=(0.1, 0.5),
+                             speed_per_halfturn=G.N / 64, sphere=(10.0, 60.0, 0.5))
+    t0 = time.perf_counter()
+    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=2, device="cuda")
+    torch.cuda.synchronize()
+    log(f"sinogram synthesised in {time.perf_counter() - t0:.1f} s")
+    f = torch.zeros(G.f_shape, device=dev)
+    plan = rt4d.Plan(G)
+    # step sizes from the default rule: power iteration for |R_T| (20 steps)
+    j0 = rt4d.Job(plan, g, f, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=2)
+    rep0 = j0.report()
+    j0.close()
+    L_R = rep0["L_R"]
+    lam1 = 2.0 ** -9 * L_R * L_R
+    log(f"L_R {L_R:.6g} L_G {rep0['L_G']:.6g} tau=sigma {rep0['tau']:.6g} lambda1 {lam1:.6g}")
+    job = rt4d.Job(plan, g, f, lambda1=lam1, lambda2=4.0, n_iter=args.warmup + args.steps,
+                   tau=rep0["tau"], sigma=rep0["sigma"], check_every=1)
+    for _ in range(args.warmup):
+        job.step(1)
+    torch.cuda.synchronize()
+    rt4d.timing_reset()
+    rt4d.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        job.step(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rt4d.timing_enable(False)
+    per = {}
+    for k in KERNELS + ("k_tv_norm",):
+        ms, n = rt4d.timing_read(k)
+        if n:
+            per[k] = (ms, n)
+    rt4d.timing_reset()
+    rep = job.report()
+    job.close()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    samples = 2.0 * G.Ntheta * G.Nz * G.Ns * G.N
+    value = samples / (ms_step * 1e-3) / 1e9
+    log("per-kernel ms/launch: " + ", ".join(f"{k} {v[0] / v[1]:.3f}" for k, v in per.items()))
+    log(f"final residual {rep['residual']:.6g} objective {rep['objective']:.6g} "
+        f"rel_change {rep['rel_change']:.3g}")
+
+    dom = max((k for k in per if k in KERNELS), key=lambda k: per[k][0])
+    bound, work = algorithmic(dom, G)
+    dur = per[dom][0] / per[dom][1] * 1e-3
+    if bound == "hbm":
+        achieved, peak, unit = work / dur / 1e9, PEAK_HBM / 1e9, "GB/s"
+    else:
+        achieved, peak, unit = work / dur / 1e12, PEAK_FP32_VALU / 1e12, "TFLOP/s"
+    roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom),
+            "launch_ms": round(dur * 1e3, 4)}
+    kern = {}
+    for k, (ms, n) in per.items():
+        if k not in KERNELS:
+            continue
+        b, w = algorithmic(k, G)
+        d = ms / n * 1e-3
+        kern[k] = {"ms": round(d * 1e3, 4), "bound": b,
+                   "frac": round((w / d) / (PEAK_HBM if b == "hbm" else PEAK_FP32_VALU), 4)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gray-samples/s (1e9 ray-samples/s)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain FP32 R_T/R_T* + 4D TV Chambolle-Pock iteration, "
+                               "512x512x128 volume, K=16 cosine basis, 1800 projections over "
+                               "10 half-turns, 512 bins, 10 TV frames, 40 moving ellipsoids + "
+                               "growing sphere, 1% noise",
+                   "N": G.N, "Nz": G.Nz, "Ns": G.Ns, "Ntheta": G.Ntheta, "Npi": G.Npi, "K": G.K,
+                   "Nt": G.Nt, "form": "PF", "precision": "fp32", "parallelism": "single GPU"},
+        "iters_per_s": round(1e3 / ms_step, 4),
+        "roofline": roof, "kernels": kern,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one slice ...")
+        out["cpu_baseline"] = cpu_baseline(G, g[:, 0:1, :].cpu().numpy(), 3)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,168 @@
+// Internal declarations of librt4d: plan and job state, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rt4d.h"
+
+namespace rt {
+
+// ------------------------------------------------------------------ errors
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+#define RT_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::rt::hip_fail(e_, #call);   \
+    } while (0)
+
+// Records HIP events around one kernel launch when timing is enabled
+// (rt_timing_enable); construct right before the launch, stop() right after.
+class KTimer {
+  public:
+    KTimer(const char *name, hipStream_t s);
+    void stop();
+    ~KTimer();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_{}, b_{};
+    bool live_ = false;
+};
+
+// ------------------------------------------------------------- host tables
+struct Tables {
+    std::vector<double> theta, t;       // [Ntheta]
+    std::vector<int32_t> cls, rot, flip;
+    std::vector<double> phi;            // [Ntheta][K]
+    std::vector<double> S;              // [Nt][K]
+    std::vector<double> ccos, csin;     // [Ntheta0] cos/sin of theta0_a
+};
+
+// Work layout of the ray-driven projector: classes of one walk direction
+// (rows when |cos| >= |sin|, columns otherwise) are grouped A at a time; one
+// workgroup owns (group, slice, channel chunk, bin tile).
+struct FwdCfg {
+    int A = 1;            // classes per group
+    int ngroups = 0;
+    int KC = 4;           // channels per chunk (4, 8, 16)
+    int nkc = 1;          // channel chunks
+    int BT = 1;           // bins per tile
+    int nbt = 1;          // bin tiles
+    int stride = 4;       // floats per staged position (KC + padding)
+    int vec = 1;          // 4: float4 staging loads
+    size_t lds = 0;       // bytes of LDS per workgroup
+};
+
+struct AdjCfg {
+    int KC = 4, nkc = 1, stride = 4, vec = 1;
+    int TQ = 32, TR = 32; // pixel tile
+    int CA = 8;           // classes staged per round
+    int WMAX = 0;         // bins of the widest staged window
+    size_t lds = 0;
+};
+
+struct TvCfg {
+    int KT = 8;           // compile-time channel bound (8, 16, 32, 64)
+};
+
+struct Plan {
+    rt_geom g{};
+    rt_form form = RT_FORM_PF;
+    rt_prec prec = RT_PREC_FP32;
+    int device = 0;
+    int n0 = 1;           // Ntheta0 = Ntheta / Npi
+    Tables T;
+    FwdCfg fwd;
+    AdjCfg adj;
+    TvCfg tv;
+
+    float *d_phi = nullptr;     // [Ntheta][K]
+    float *d_S = nullptr;       // [Nt][K]
+    double *d_ccos = nullptr;   // [Ntheta0]
+    double *d_csin = nullptr;
+    int *d_gcls = nullptr;      // [ngroups][A], -1 = empty slot
+    int *d_gwalk = nullptr;     // [ngroups]
+    float *d_scr = nullptr;     // [Ntheta0][Nz][Ns][K]: P (forward), g~ (adjoint)
+    double *d_part = nullptr;   // FP64 partial sums
+    size_t part_cap = 0;        // doubles in d_part
+    double *d_red = nullptr;    // final FP64 sums (16 doubles)
+    size_t bytes = 0;
+};
+
+struct Job {
+    const Plan *plan = nullptr;
+    rt_solve_params prm{};
+    const float *g = nullptr;
+    float *f = nullptr;
+    float *ft = nullptr;        // extrapolated primal f~
+    float *h1 = nullptr;        // dual of the data term, sinogram shaped
+    float *h2 = nullptr;        // dual of the TV term, [Nz][N][N][Nt][4]
+    float *work = nullptr;      // R_T* h1, coefficient shaped
+    float *sino = nullptr;      // R_T f for the report, sinogram shaped
+    double tau = 0, sigma = 0, L_R = 0, L_G = 0;
+    int iters = 0;
+    bool stopped = false;
+    double residual = 0, objective = 0, rel_change = 0;
+    size_t bytes = 0;
+};
+
+// ------------------------------------------------------------ sizes/helpers
+inline size_t nf_of(const rt_geom &g) { return (size_t)g.Nz * g.N * g.N * g.K; }
+inline size_t ng_of(const rt_geom &g) { return (size_t)g.Ntheta * g.Nz * g.Ns; }
+inline size_t n4_of(const rt_geom &g) { return (size_t)g.Nz * g.N * g.N * g.Nt; }
+size_t job_state_bytes(const rt_geom &g);
+size_t plan_scratch_bytes(const rt_geom &g);
+
+int check_geom(const rt_geom *g);
+int check_plan(const rt_plan *p);
+
+// ---------------------------------------------------------------- launchers
+// Projector (proj_pf.hip).  mode of the contraction epilogue:
+enum ContractMode { CONTRACT_STORE = 0, CONTRACT_PROX = 1 };
+int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                      float *h1, float sigma, double *part, hipStream_t s);
+int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s);
+int forward_partials(const Plan &p);      // workgroups (= FP64 partials) of the h1 prox
+unsigned voxel_blocks(const rt_geom &g);  // workgroups (= partials) of the voxel kernels
+
+// 4D TV (tv.hip)
+int launch_tv_grad(const Plan &p, const float *f, float lambda2, float *pout, hipStream_t s);
+int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hipStream_t s);
+int launch_shrink(const Plan &p, float *pio, float lambda1, size_t n4, hipStream_t s);
+// h2 <- shrink(h2 + sigma grad S f~); FP64 partial sum of |grad S f~| per block
+int launch_grad_shrink(const Plan &p, const float *ft, float *h2, float sigma, float lambda1,
+                       float lambda2, double *part, hipStream_t s);
+// f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; partials |f+ - f|^2, |f+|^2
+int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
+                      float tau, float lambda2, double *part, hipStream_t s);
+// sum over voxels and frames of |grad S f| (FP64 partials)
+int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s);
+
+// Reductions and vector helpers (reduce.hip)
+int reduce_blocks(int nblocks_hint, size_t n);
+int launch_dot_partials(const float *x, const float *y, size_t n, double *part, int nblocks,
+                        hipStream_t s);
+int launch_diff_sq_partials(const float *x, const float *y, size_t n, double *part, int nblocks,
+                            hipStream_t s);
+// out[j] = sum over i < nb of part[i*stride + j], j < width (fixed order)
+int launch_finish(const double *part, int nb, int width, double *out, hipStream_t s);
+int launch_fill(float *x, float v, size_t n, hipStream_t s);
+int launch_scale(float *x, const double *num_den, size_t n, hipStream_t s);
+int launch_copy(float *dst, const float *src, size_t n, hipStream_t s);
+int launch_seeded_uniform(float *x, size_t n, uint64_t seed, hipStream_t s);
+
+}  // namespace rt
+
+struct rt_plan {
+    rt::Plan impl;
+};
+struct rt_job {
+    rt::Job impl;
+};

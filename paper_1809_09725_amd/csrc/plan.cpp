@@ -1,0 +1,285 @@
+// Plan: geometry checks, host tables, kernel configuration, device tables.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace rt {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? RT_E_OOM : RT_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+int check_geom(const rt_geom *g)
+{
+    if (!g) return fail(RT_E_ARG, "geometry pointer is NULL");
+    if (g->N < 1 || g->Ns < 1 || g->Ntheta < 1 || g->Npi < 1 || g->K < 1 || g->Nt < 1 ||
+        g->Nz < 0)
+        return fail(RT_E_SHAPE, "sizes must be >= 1 (Nz >= 0): N=%d Nz=%d Ns=%d Ntheta=%d "
+                    "Npi=%d K=%d Nt=%d", g->N, g->Nz, g->Ns, g->Ntheta, g->Npi, g->K, g->Nt);
+    if (g->Ntheta % g->Npi != 0)
+        return fail(RT_E_SHAPE, "Ntheta=%d is not a whole number of half-turns Npi=%d",
+                    g->Ntheta, g->Npi);
+    if (g->Nt > g->Npi)
+        return fail(RT_E_SHAPE, "Nt=%d time frames exceed the Npi=%d half-turns", g->Nt, g->Npi);
+    if (g->N > 4096 || g->Ns > 8192 || g->K > 64 || g->Nt > 64)
+        return fail(RT_E_SHAPE, "size beyond the supported maximum (N<=4096, Ns<=8192, "
+                    "K<=64, Nt<=64)");
+    return RT_OK;
+}
+
+int check_plan(const rt_plan *p)
+{
+    if (!p) return fail(RT_E_ARG, "plan is NULL");
+    return RT_OK;
+}
+
+size_t plan_scratch_bytes(const rt_geom &g)
+{
+    const size_t n0 = (size_t)(g.Ntheta / g.Npi);
+    return n0 * g.Nz * g.Ns * g.K * sizeof(float);
+}
+
+size_t job_state_bytes(const rt_geom &g)
+{
+    return (2 * nf_of(g) + 2 * ng_of(g) + 4 * n4_of(g)) * sizeof(float);
+}
+
+// Sec. 4, eq. discrt: theta_i = i*pi/Ntheta0, t_i = i/Ntheta (theta = alpha t,
+// alpha = Npi*pi); the class a = i mod Ntheta0 of [0,pi) and the half-turn
+// rot = i div Ntheta0 of the pi-periodicity identity.
+static void build_tables(const rt_geom &g, const double *phi, const double *S, Tables &T)
+{
+    const int n0 = g.Ntheta / g.Npi;
+    T.theta.resize(g.Ntheta);
+    T.t.resize(g.Ntheta);
+    T.cls.resize(g.Ntheta);
+    T.rot.resize(g.Ntheta);
+    T.flip.resize(g.Ntheta);
+    T.phi.resize((size_t)g.Ntheta * g.K);
+    for (int i = 0; i < g.Ntheta; ++i) {
+        T.theta[i] = ((double)i * M_PI) / (double)n0;
+        T.t[i] = (double)i / (double)g.Ntheta;
+        T.cls[i] = i % n0;
+        T.rot[i] = i / n0;
+        T.flip[i] = (i / n0) & 1;
+        for (int k = 0; k < g.K; ++k)
+            T.phi[(size_t)i * g.K + k] =
+                phi ? phi[(size_t)i * g.K + k] : std::cos(M_PI * (double)k * T.t[i]);
+    }
+    T.S.resize((size_t)g.Nt * g.K);
+    for (int m = 0; m < g.Nt; ++m)
+        for (int k = 0; k < g.K; ++k)
+            T.S[(size_t)m * g.K + k] = S ? S[(size_t)m * g.K + k] : T.phi[(size_t)m * n0 * g.K + k];
+    T.ccos.resize(n0);
+    T.csin.resize(n0);
+    for (int a = 0; a < n0; ++a) {
+        T.ccos[a] = std::cos(T.theta[a]);
+        T.csin[a] = std::sin(T.theta[a]);
+    }
+}
+
+static int pick_kc(int K, int positions, size_t budget, int *KC, int *stride)
+{
+    const int K4 = (K + 3) / 4 * 4;
+    for (int kc : {16, 8, 4}) {
+        if (kc > K4 && kc != 4) continue;
+        for (int pad : {4, 0}) {
+            const size_t need = (size_t)positions * (kc + pad) * sizeof(float);
+            if (need <= budget) {
+                *KC = kc;
+                *stride = kc + pad;
+                return 0;
+            }
+        }
+    }
+    return -1;
+}
+
+static int configure(Plan &p)
+{
+    const rt_geom &g = p.g;
+    const int n0 = p.n0;
+    const size_t budget = 80 * 1024;
+
+    // ---- forward: classes grouped by walk direction
+    std::vector<int> rows, cols;
+    for (int a = 0; a < n0; ++a)
+        (std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? rows : cols).push_back(a);
+    FwdCfg &F = p.fwd;
+    const int pairs_max = 256 * 8;
+    F.BT = std::min(g.Ns, pairs_max);
+    F.nbt = (g.Ns + F.BT - 1) / F.BT;
+    F.A = std::max(1, pairs_max / F.BT);
+    F.A = std::min(F.A, (int)std::max(rows.size(), cols.size()));
+    std::vector<int> gcls, gwalk;
+    for (int w = 0; w < 2; ++w) {
+        const std::vector<int> &L = w == 0 ? rows : cols;
+        for (size_t i = 0; i < L.size(); i += F.A) {
+            for (int j = 0; j < F.A; ++j)
+                gcls.push_back(i + j < L.size() ? L[i + j] : -1);
+            gwalk.push_back(w);
+        }
+    }
+    F.ngroups = (int)gwalk.size();
+    if (pick_kc(g.K, g.N + 2, budget, &F.KC, &F.stride))
+        return fail(RT_E_SHAPE, "N=%d too large for the projector's staging buffer", g.N);
+    F.nkc = (g.K + F.KC - 1) / F.KC;
+    F.vec = (g.K % 4 == 0) ? 4 : 1;
+    F.lds = (size_t)(g.N + 2) * F.stride * sizeof(float);
+
+    // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
+    AdjCfg &B = p.adj;
+    B.TQ = 32;
+    B.TR = 32;
+    B.CA = 8;
+    int wmax = 2;
+    for (int a = 0; a < n0; ++a) {
+        const double span = (B.TQ - 1) * std::fabs(p.T.ccos[a]) + (B.TR - 1) * std::fabs(p.T.csin[a]);
+        wmax = std::max(wmax, (int)std::ceil(span) + 4);
+    }
+    B.WMAX = wmax;
+    if (pick_kc(g.K, B.CA * B.WMAX, budget, &B.KC, &B.stride))
+        return fail(RT_E_SHAPE, "back-projection staging does not fit");
+    B.nkc = (g.K + B.KC - 1) / B.KC;
+    B.vec = (g.K % 4 == 0) ? 4 : 1;
+    B.lds = (size_t)B.CA * B.WMAX * B.stride * sizeof(float);
+
+    p.tv.KT = g.K <= 8 ? 8 : g.K <= 16 ? 16 : g.K <= 32 ? 32 : 64;
+
+    // device copies of the group tables
+    RT_HIP(hipMalloc(&p.d_gcls, gcls.size() * sizeof(int)));
+    RT_HIP(hipMalloc(&p.d_gwalk, gwalk.size() * sizeof(int)));
+    RT_HIP(hipMemcpy(p.d_gcls, gcls.data(), gcls.size() * sizeof(int), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p.d_gwalk, gwalk.data(), gwalk.size() * sizeof(int), hipMemcpyHostToDevice));
+    p.bytes += (gcls.size() + gwalk.size()) * sizeof(int);
+    return RT_OK;
+}
+
+static void free_plan(Plan &p)
+{
+    for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
+                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_scr, (void *)p.d_part,
+                      (void *)p.d_red})
+        if (ptr) (void)hipFree(ptr);
+}
+
+template <class T>
+static int dev_copy(T **dst, const std::vector<T> &src, size_t *bytes)
+{
+    const size_t b = std::max<size_t>(src.size(), 1) * sizeof(T);
+    RT_HIP(hipMalloc(dst, b));
+    if (!src.empty()) RT_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    *bytes += b;
+    return RT_OK;
+}
+
+static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double *phi,
+                  const double *S, Plan &p)
+{
+    p.g = *geom;
+    p.form = form;
+    p.prec = prec;
+    p.n0 = geom->Ntheta / geom->Npi;
+    RT_HIP(hipGetDevice(&p.device));
+    build_tables(p.g, phi, S, p.T);
+    int rc = configure(p);
+    if (rc) return rc;
+    std::vector<float> phi32(p.T.phi.begin(), p.T.phi.end()), S32(p.T.S.begin(), p.T.S.end());
+    if ((rc = dev_copy(&p.d_phi, phi32, &p.bytes))) return rc;
+    if ((rc = dev_copy(&p.d_S, S32, &p.bytes))) return rc;
+    if ((rc = dev_copy(&p.d_ccos, p.T.ccos, &p.bytes))) return rc;
+    if ((rc = dev_copy(&p.d_csin, p.T.csin, &p.bytes))) return rc;
+    const size_t scr = std::max<size_t>(plan_scratch_bytes(p.g), 256);
+    RT_HIP(hipMalloc(&p.d_scr, scr));
+    p.bytes += scr;
+    p.part_cap = (size_t)1 << 18;
+    RT_HIP(hipMalloc(&p.d_part, p.part_cap * sizeof(double)));
+    RT_HIP(hipMalloc(&p.d_red, 16 * sizeof(double)));
+    p.bytes += (p.part_cap + 16) * sizeof(double);
+    return RT_OK;
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" int rt_plan_create(const rt_geom *geom, rt_form form, rt_prec prec, const double *phi,
+                              const double *S, rt_plan **out)
+{
+    if (!out) return fail(RT_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (form != RT_FORM_PF && form != RT_FORM_SF) return fail(RT_E_ARG, "unknown form %d", (int)form);
+    if (prec != RT_PREC_FP32 && prec != RT_PREC_BF16MFMA)
+        return fail(RT_E_ARG, "unknown precision %d", (int)prec);
+    if (prec == RT_PREC_BF16MFMA && form != RT_FORM_SF)
+        return fail(RT_E_ARG, "the BF16 contraction needs the synthesise-first form");
+    if (form == RT_FORM_SF) return fail(RT_E_ARG, "synthesise-first form is not available yet");
+    if (phi)
+        for (size_t e = 0; e < (size_t)geom->Ntheta * geom->K; ++e)
+            if (!std::isfinite(phi[e])) return fail(RT_E_ARG, "phi has a non-finite entry");
+    if (S)
+        for (size_t e = 0; e < (size_t)geom->Nt * geom->K; ++e)
+            if (!std::isfinite(S[e])) return fail(RT_E_ARG, "S has a non-finite entry");
+    rt_plan *p = new (std::nothrow) rt_plan();
+    if (!p) return fail(RT_E_OOM, "host allocation failed");
+    rc = create(geom, form, prec, phi, S, p->impl);
+    if (rc) {
+        free_plan(p->impl);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return RT_OK;
+}
+
+extern "C" void rt_plan_destroy(rt_plan *p)
+{
+    if (!p) return;
+    free_plan(p->impl);
+    delete p;
+}
+
+extern "C" int rt_plan_bytes(const rt_plan *p, size_t *bytes)
+{
+    if (check_plan(p) || !bytes) return fail(RT_E_ARG, "NULL argument");
+    *bytes = p->impl.bytes;
+    return RT_OK;
+}
+
+extern "C" int rt_tables(const rt_plan *p, double *theta, double *t, int32_t *cls, int32_t *rot,
+                         int32_t *flip)
+{
+    if (check_plan(p)) return RT_E_ARG;
+    const Tables &T = p->impl.T;
+    const size_t n = T.theta.size();
+    if (theta) std::memcpy(theta, T.theta.data(), n * sizeof(double));
+    if (t) std::memcpy(t, T.t.data(), n * sizeof(double));
+    if (cls) std::memcpy(cls, T.cls.data(), n * sizeof(int32_t));
+    if (rot) std::memcpy(rot, T.rot.data(), n * sizeof(int32_t));
+    if (flip) std::memcpy(flip, T.flip.data(), n * sizeof(int32_t));
+    return RT_OK;
+}
+
+extern "C" const char *rt_last_error(void) { return rt::g_err.c_str(); }

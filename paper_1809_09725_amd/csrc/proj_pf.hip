@@ -1,0 +1,444 @@
+// Project-first (PF) FP32 form of the decomposed-time Radon operator and its
+// transpose (Sec. 4, eqs. radapr and radadjapr, with the pi-periodicity
+// identity and the fold-sum).
+//
+// Forward  g(i,z,b) = sum_k Phi[i][k] P(a(i), z, b'(i,b), k)
+//          P(a,z,b,k) = static projection of f_k at theta0_a in [0,pi)
+//          b' = b on even half-turns, Ns-1-b on odd ones (s_{Ns-1-b} = -s_b)
+// Adjoint  g~(a,z,b,k) = sum_rot Phi[rot*Ntheta0+a][k] g(rot*Ntheta0+a, z, b')
+//          out_k = static back-projection of g~(.,.,.,k) over theta0_a
+//
+// Kernels
+//   k_project      ray-driven projection of a chunk of KC channels for a
+//                  group of angle classes of one walk direction; each line
+//                  (row or column) of the slice is staged once in LDS and
+//                  shared by all rays of the group.
+//   k_contract     sum over k with the s-flip; optionally fused with the
+//                  h1 prox of Fig. 2 and an FP64 partial of |R f~ - g|^2.
+//   k_fold         the fold-sum g -> g~.
+//   k_backproject  pixel-driven back-projection: a 32x32 pixel tile stages
+//                  the detector window each class needs in LDS.
+// Ray positions are computed in FP64 (the rate of FP64 FMA on CDNA4 equals
+// that of unpacked FP32), weights and accumulation in FP32.
+#include "common.h"
+#include "internal.h"
+
+namespace rt {
+namespace {
+
+template <int KC, int PPT, int VEC>
+__global__ __launch_bounds__(NT, 2) void k_project(
+    const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
+    const int *__restrict__ gwalk, const double *__restrict__ ccos,
+    const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
+    int nbt, int nkc, int stride, unsigned nblocks)
+{
+    extern __shared__ float line[];   // [N + 2 positions][stride], positions -1 .. N
+    unsigned lid = xcd_remap(blockIdx.x, nblocks);
+    const int bt = lid % nbt;
+    lid /= nbt;
+    const int kc = lid % nkc;
+    lid /= nkc;
+    const int grp = lid % ngroups;
+    const int z = lid / ngroups;
+    const int tid = threadIdx.x;
+    const int walk = gwalk[grp];
+    const int k0 = kc * KC;
+    const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
+
+    double base[PPT], slope[PPT];
+    float invc[PPT];
+    int cls[PPT], bin[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int pr = tid + NT * j;
+        const int slot = pr / BT;
+        const int b = bt * BT + pr % BT;
+        const int a = slot < A ? gcls[grp * A + slot] : -1;
+        cls[j] = (a >= 0 && b < Ns) ? a : -1;
+        bin[j] = b;
+        base[j] = -1.0e9;   // far outside: both taps get weight 0
+        slope[j] = 0.0;
+        invc[j] = 0.f;
+        if (cls[j] >= 0) {
+            const double cs = ccos[a], sn = csin[a], sb = (double)b - hS;
+            if (walk == 0) {   // |cos| >= |sin|: the ray crosses every row once
+                base[j] = sb / cs + hN;
+                slope[j] = -sn / cs;
+                invc[j] = (float)(1.0 / fabs(cs));
+            } else {           // |sin| > |cos|: every column once
+                base[j] = sb / sn + hN;
+                slope[j] = -cs / sn;
+                invc[j] = (float)(1.0 / fabs(sn));
+            }
+        }
+    }
+
+    float acc[PPT][KC];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[j][k] = 0.f;
+
+    for (int e = tid; e < 2 * stride; e += NT)   // zero positions -1 and N
+        line[(e < stride ? 0 : (N + 1) * stride) + e % stride] = 0.f;
+
+    const size_t zoff = (size_t)z * N * N * K;
+    const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;   // next line
+    const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;   // next position
+
+    for (int l = 0; l < N; ++l) {
+        __syncthreads();
+        const float *src = f + zoff + (size_t)l * lstep + k0;
+        if (VEC == 4) {
+            constexpr int NQ = KC / 4;
+            for (int e = tid; e < N * NQ; e += NT) {
+                const int pos = e / NQ, kq = e % NQ;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k0 + 4 * kq < K) v = *(const float4 *)(src + (size_t)pos * pstep + 4 * kq);
+                *(float4 *)(line + (pos + 1) * stride + 4 * kq) = v;
+            }
+        } else {
+            for (int e = tid; e < N * KC; e += NT) {
+                const int pos = e / KC, kk = e % KC;
+                line[(pos + 1) * stride + kk] = (k0 + kk < K) ? src[(size_t)pos * pstep + kk] : 0.f;
+            }
+        }
+        __syncthreads();
+        const double lc = (double)l - hN;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const double u = fma(lc, slope[j], base[j]);   // position along the line
+            const double fl = floor(u);
+            const int q0 = (int)fl;
+            const float fr = (float)(u - fl);
+            const bool in = (q0 >= -1) && (q0 < N);
+            const float w1 = in ? fr * invc[j] : 0.f;
+            const float w0 = in ? (1.f - fr) * invc[j] : 0.f;
+            const float *t0 = line + (in ? q0 + 1 : 0) * stride;
+#pragma unroll
+            for (int k = 0; k < KC; k += 4) {
+                const float4 x0 = *(const float4 *)(t0 + k);
+                const float4 x1 = *(const float4 *)(t0 + stride + k);
+                acc[j][k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, acc[j][k + 0]));
+                acc[j][k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, acc[j][k + 1]));
+                acc[j][k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, acc[j][k + 2]));
+                acc[j][k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, acc[j][k + 3]));
+            }
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (cls[j] < 0) continue;
+        float *dst = P + (((size_t)cls[j] * Nz + z) * Ns + bin[j]) * K + k0;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k0 + k < K) dst[k] = acc[j][k];
+    }
+}
+
+// g(i,z,b) = sum_k Phi[i][k] P(a(i), z, b', k); rows (i,z) grid-strided over a
+// fixed number of workgroups so the FP64 partials have a fixed order.
+__global__ __launch_bounds__(NT) void k_contract(
+    const float *__restrict__ P, const float *__restrict__ phi, float *__restrict__ out,
+    const float *__restrict__ gdata, int mode, float sigma, double *__restrict__ part, int Nz,
+    int Ns, int K, int n0, int Ntheta)
+{
+    __shared__ double sh[NT / 64];
+    const long rows = (long)Ntheta * Nz;
+    double d2 = 0.0;
+    const float inv1s = 1.f / (1.f + sigma);
+    for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int i = (int)(row / Nz), z = (int)(row % Nz);
+        const int a = i % n0, rot = i / n0;
+        const float *ph = phi + (size_t)i * K;
+        const float *Pz = P + ((size_t)a * Nz + z) * Ns * K;
+        float *o = out + ((size_t)i * Nz + z) * Ns;
+        for (int b = threadIdx.x; b < Ns; b += NT) {
+            const int bp = (rot & 1) ? Ns - 1 - b : b;
+            const float *src = Pz + (size_t)bp * K;
+            float v = 0.f;
+            if ((K & 3) == 0) {
+                for (int k = 0; k < K; k += 4) {
+                    const float4 x = *(const float4 *)(src + k);
+                    v = fmaf(ph[k], x.x, v);
+                    v = fmaf(ph[k + 1], x.y, v);
+                    v = fmaf(ph[k + 2], x.z, v);
+                    v = fmaf(ph[k + 3], x.w, v);
+                }
+            } else {
+                for (int k = 0; k < K; ++k) v = fmaf(ph[k], src[k], v);
+            }
+            if (mode == CONTRACT_STORE) {
+                o[b] = v;
+            } else {   // Fig. 2 step 3: h1 <- (h1 + sigma (R f~ - g)) / (1 + sigma)
+                const float d = v - gdata[((size_t)i * Nz + z) * Ns + b];
+                d2 += (double)d * (double)d;
+                o[b] = (o[b] + sigma * d) * inv1s;
+            }
+        }
+    }
+    if (part) {
+        const double s = block_sum(d2, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    }
+}
+
+// g~(a,z,b,k) = sum_rot Phi[rot*n0+a][k] g(rot*n0+a, z, b')  (fold-sum, Sec. 4)
+template <int KT>
+__global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
+                                             const float *__restrict__ phi,
+                                             float *__restrict__ gt, int Nz, int Ns, int K,
+                                             int n0, int Npi)
+{
+    const long rows = (long)n0 * Nz;
+    for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int a = (int)(row / Nz), z = (int)(row % Nz);
+        for (int b = threadIdx.x; b < Ns; b += NT) {
+            float acc[KT];
+#pragma unroll
+            for (int k = 0; k < KT; ++k) acc[k] = 0.f;
+            for (int rot = 0; rot < Npi; ++rot) {
+                const int i = rot * n0 + a;
+                const int bp = (rot & 1) ? Ns - 1 - b : b;
+                const float v = g[((size_t)i * Nz + z) * Ns + bp];
+                const float *ph = phi + (size_t)i * K;
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (k < K) acc[k] = fmaf(ph[k], v, acc[k]);
+            }
+            float *dst = gt + (((size_t)a * Nz + z) * Ns + b) * K;
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+                if (k < K) dst[k] = acc[k];
+        }
+    }
+}
+
+constexpr int BP_VPT = 4;     // pixels per thread (rows 8 apart)
+constexpr int BP_MAXCA = 16;  // classes staged per round, at most
+
+template <int KC, int VEC>
+__global__ __launch_bounds__(NT, 2) void k_backproject(
+    const float *__restrict__ gt, float *__restrict__ out, const double *__restrict__ ccos,
+    const double *__restrict__ csin, int N, int Nz, int Ns, int K, int n0, int nkc, int ntq,
+    int ntr, int CA, int WMAX, int stride, unsigned nblocks)
+{
+    extern __shared__ float win[];   // [CA][WMAX][stride]
+    __shared__ int s_wlo[BP_MAXCA], s_w[BP_MAXCA];
+    unsigned lid = xcd_remap(blockIdx.x, nblocks);
+    const int tq = lid % ntq;
+    lid /= ntq;
+    const int tr = lid % ntr;
+    lid /= ntr;
+    const int kc = lid % nkc;
+    const int z = lid / nkc;
+    const int tid = threadIdx.x;
+    const int k0 = kc * KC;
+    const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
+
+    const int q = tq * 32 + (tid & 31);
+    const double x = (double)q - hN;
+    double y[BP_VPT];
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j) y[j] = (double)(tr * 32 + (tid >> 5) + 8 * j) - hN;
+    const double xlo = (double)(tq * 32) - hN, xhi = xlo + 31.0;
+    const double ylo = (double)(tr * 32) - hN, yhi = ylo + 31.0;
+
+    float acc[BP_VPT][KC];
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[j][k] = 0.f;
+
+    for (int a0 = 0; a0 < n0; a0 += CA) {
+        const int nca = min(CA, n0 - a0);
+        __syncthreads();
+        if (tid < nca) {
+            // detector window of class a over the tile: s_p is affine in
+            // (x, y) and each rounding step is monotone, so the extreme
+            // positions of the tile's pixels are at its corners
+            const double cs = ccos[a0 + tid], sn = csin[a0 + tid];
+            const double u00 = fma(xlo, cs, fma(ylo, sn, hS));
+            const double u10 = fma(xhi, cs, fma(ylo, sn, hS));
+            const double u01 = fma(xlo, cs, fma(yhi, sn, hS));
+            const double u11 = fma(xhi, cs, fma(yhi, sn, hS));
+            const double umin = fmin(fmin(u00, u10), fmin(u01, u11));
+            const double umax = fmax(fmax(u00, u10), fmax(u01, u11));
+            const int lo = (int)floor(umin);
+            s_wlo[tid] = lo;
+            s_w[tid] = (int)floor(umax) + 2 - lo;
+        }
+        __syncthreads();
+        if (VEC == 4) {
+            constexpr int NQ = KC / 4;
+            for (int e = tid; e < nca * WMAX * NQ; e += NT) {
+                const int c = e / (WMAX * NQ), r = e % (WMAX * NQ);
+                const int w = r / NQ, kq = r % NQ;
+                const int b = s_wlo[c] + w;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (w < s_w[c] && b >= 0 && b < Ns && k0 + 4 * kq < K)
+                    v = *(const float4 *)(gt + (((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + 4 * kq);
+                *(float4 *)(win + (c * WMAX + w) * stride + 4 * kq) = v;
+            }
+        } else {
+            for (int e = tid; e < nca * WMAX * KC; e += NT) {
+                const int c = e / (WMAX * KC), r = e % (WMAX * KC);
+                const int w = r / KC, kk = r % KC;
+                const int b = s_wlo[c] + w;
+                float v = 0.f;
+                if (w < s_w[c] && b >= 0 && b < Ns && k0 + kk < K)
+                    v = gt[(((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + kk];
+                win[(c * WMAX + w) * stride + kk] = v;
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < nca; ++c) {
+            const double cs = ccos[a0 + c], sn = csin[a0 + c];
+            const float invc = (float)(1.0 / fmax(fabs(cs), fabs(sn)));
+            const int wlo = s_wlo[c];
+            const float *wc = win + c * WMAX * stride;
+#pragma unroll
+            for (int j = 0; j < BP_VPT; ++j) {
+                const double u = fma(x, cs, fma(y[j], sn, hS));   // s_p in bin units
+                const double fl = floor(u);
+                const float fr = (float)(u - fl);
+                // triangle weights of the bins floor(u) and floor(u)+1
+                const float w0 = fmaxf(0.f, 1.f - fr * invc) * invc;
+                const float w1 = fmaxf(0.f, 1.f - (1.f - fr) * invc) * invc;
+                const float *t0 = wc + ((int)fl - wlo) * stride;
+#pragma unroll
+                for (int k = 0; k < KC; k += 4) {
+                    const float4 x0 = *(const float4 *)(t0 + k);
+                    const float4 x1 = *(const float4 *)(t0 + stride + k);
+                    acc[j][k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, acc[j][k + 0]));
+                    acc[j][k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, acc[j][k + 1]));
+                    acc[j][k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, acc[j][k + 2]));
+                    acc[j][k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, acc[j][k + 3]));
+                }
+            }
+        }
+    }
+
+    if (q >= N) return;
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j) {
+        const int r = tr * 32 + (tid >> 5) + 8 * j;
+        if (r >= N) continue;
+        float *dst = out + (((size_t)z * N + r) * N + q) * K + k0;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k0 + k < K) dst[k] = acc[j][k];
+    }
+}
+
+template <int KC, int PPT, int VEC>
+static void launch_project_t(const Plan &p, const float *f, hipStream_t s, unsigned nb)
+{
+    const rt_geom &G = p.g;
+    const FwdCfg &F = p.fwd;
+    KTimer kt("k_project", s);
+    hipLaunchKernelGGL((k_project<KC, PPT, VEC>), dim3(nb), dim3(NT), F.lds, s, f, p.d_scr,
+                       p.d_gcls, p.d_gwalk, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A,
+                       F.ngroups, F.BT, F.nbt, F.nkc, F.stride, nb);
+    kt.stop();
+}
+
+template <int KC, int VEC>
+static void launch_project_kv(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
+{
+    switch (ppt) {
+    case 1: launch_project_t<KC, 1, VEC>(p, f, s, nb); break;
+    case 2: launch_project_t<KC, 2, VEC>(p, f, s, nb); break;
+    case 4: launch_project_t<KC, 4, VEC>(p, f, s, nb); break;
+    default: launch_project_t<KC, 8, VEC>(p, f, s, nb); break;
+    }
+}
+
+template <int KC, int VEC>
+static void launch_bp_t(const Plan &p, float *out, hipStream_t s, unsigned nb, int ntq, int ntr)
+{
+    const rt_geom &G = p.g;
+    const AdjCfg &B = p.adj;
+    KTimer kt("k_backproject", s);
+    hipLaunchKernelGGL((k_backproject<KC, VEC>), dim3(nb), dim3(NT), B.lds, s, p.d_scr, out,
+                       p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, p.n0, B.nkc, ntq, ntr, B.CA,
+                       B.WMAX, B.stride, nb);
+    kt.stop();
+}
+
+static unsigned row_blocks(long rows) { return (unsigned)std::min<long>(rows, 4096); }
+
+}  // namespace
+
+int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                      float *h1, float sigma, double *part, hipStream_t s)
+{
+    const rt_geom &G = p.g;
+    const FwdCfg &F = p.fwd;
+    if (G.Nz == 0) return RT_OK;
+    const int pairs = F.A * F.BT;
+    const int ppt = pairs <= NT ? 1 : pairs <= 2 * NT ? 2 : pairs <= 4 * NT ? 4 : 8;
+    const unsigned nb = (unsigned)G.Nz * F.ngroups * F.nkc * F.nbt;
+    if (F.vec == 4) {
+        switch (F.KC) {
+        case 4: launch_project_kv<4, 4>(p, f, s, nb, ppt); break;
+        case 8: launch_project_kv<8, 4>(p, f, s, nb, ppt); break;
+        default: launch_project_kv<16, 4>(p, f, s, nb, ppt); break;
+        }
+    } else {
+        switch (F.KC) {
+        case 4: launch_project_kv<4, 1>(p, f, s, nb, ppt); break;
+        case 8: launch_project_kv<8, 1>(p, f, s, nb, ppt); break;
+        default: launch_project_kv<16, 1>(p, f, s, nb, ppt); break;
+        }
+    }
+    RT_HIP(hipGetLastError());
+    const unsigned nbc = row_blocks((long)G.Ntheta * G.Nz);
+    float *o = mode == CONTRACT_STORE ? g : h1;
+    KTimer kt("k_contract", s);
+    hipLaunchKernelGGL(k_contract, dim3(nbc), dim3(NT), 0, s, p.d_scr, p.d_phi, o, gdata, mode,
+                       sigma, part, G.Nz, G.Ns, G.K, p.n0, G.Ntheta);
+    kt.stop();
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+int forward_partials(const Plan &p) { return (int)row_blocks((long)p.g.Ntheta * p.g.Nz); }
+
+int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s)
+{
+    const rt_geom &G = p.g;
+    const AdjCfg &B = p.adj;
+    if (G.Nz == 0) return RT_OK;
+    const unsigned nbf = row_blocks((long)p.n0 * G.Nz);
+    KTimer kt("k_fold", s);
+    switch (p.tv.KT) {
+    case 8: hipLaunchKernelGGL(k_fold<8>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
+    case 16: hipLaunchKernelGGL(k_fold<16>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
+    case 32: hipLaunchKernelGGL(k_fold<32>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
+    default: hipLaunchKernelGGL(k_fold<64>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
+    }
+    kt.stop();
+    RT_HIP(hipGetLastError());
+    const int ntq = (G.N + 31) / 32, ntr = (G.N + 31) / 32;
+    const unsigned nb = (unsigned)G.Nz * B.nkc * ntr * ntq;
+    if (B.vec == 4) {
+        switch (B.KC) {
+        case 4: launch_bp_t<4, 4>(p, out, s, nb, ntq, ntr); break;
+        case 8: launch_bp_t<8, 4>(p, out, s, nb, ntq, ntr); break;
+        default: launch_bp_t<16, 4>(p, out, s, nb, ntq, ntr); break;
+        }
+    } else {
+        switch (B.KC) {
+        case 4: launch_bp_t<4, 1>(p, out, s, nb, ntq, ntr); break;
+        case 8: launch_bp_t<8, 1>(p, out, s, nb, ntq, ntr); break;
+        default: launch_bp_t<16, 1>(p, out, s, nb, ntq, ntr); break;
+        }
+    }
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+}  // namespace rt

@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad geometry before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1809_09725_amd import rt4d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "rt4d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    L = rt4d.lib()
+    names = header_functions()
+    assert len(names) >= 20, names
+    for n in names:
+        assert hasattr(L, n), f"librt4d.so does not export {n}"
+    assert set(names) == set(rt4d.EXPORTS)
+
+
+def test_no_oracle_in_the_library():
+    """The product library must not link or embed the oracle."""
+    data = open(rt4d.LIB_PATH, "rb").read()
+    for sym in (b"or_forward_direct", b"or_adjoint_direct", b"or_solve", b"liboracle"):
+        assert sym not in data
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(Ntheta=10, Npi=3), rt4d.RT_E_SHAPE),        # not whole half-turns
+    (dict(Nt=9, Npi=8), rt4d.RT_E_SHAPE),             # more frames than half-turns
+    (dict(N=0), rt4d.RT_E_SHAPE),
+    (dict(K=0), rt4d.RT_E_SHAPE),
+    (dict(Nz=-1), rt4d.RT_E_SHAPE),
+    (dict(K=65), rt4d.RT_E_SHAPE),
+])
+def test_bad_geometry_rejected_before_any_launch(bad, code):
+    g = dict(N=16, Nz=2, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
+    g.update(bad)
+    geom = rt4d.Geom(**g)
+    b = ctypes.c_size_t()
+    rc = rt4d.lib().rt_job_bytes(ctypes.byref(geom.c()), 0, 0, ctypes.byref(b))
+    assert rc == code
+    assert rt4d.lib().rt_last_error().decode()
+    h = ctypes.c_void_p()
+    rc = rt4d.lib().rt_plan_create(ctypes.byref(geom.c()), 0, 0, None, None, ctypes.byref(h))
+    assert rc == code and not h.value
+
+
+def test_bad_enums_rejected():
+    geom = rt4d.Geom(N=16, Nz=2, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
+    h = ctypes.c_void_p()
+    assert rt4d.lib().rt_plan_create(ctypes.byref(geom.c()), 7, 0, None, None, ctypes.byref(h)) == rt4d.RT_E_ARG
+    assert rt4d.lib().rt_plan_create(ctypes.byref(geom.c()), 0, 9, None, None, ctypes.byref(h)) == rt4d.RT_E_ARG
+    # BF16 contraction only exists in the synthesise-first form
+    assert rt4d.lib().rt_plan_create(ctypes.byref(geom.c()), rt4d.RT_FORM_PF, rt4d.RT_PREC_BF16MFMA,
+                                     None, None, ctypes.byref(h)) == rt4d.RT_E_ARG
+
+
+def test_job_bytes_accounts_for_state():
+    geom = rt4d.Geom(N=512, Nz=128, Ns=512, Ntheta=1800, Npi=10, K=16, Nt=10)
+    b = rt4d.rt_job_bytes(geom)
+    nf = 128 * 512 * 512 * 16
+    ng = 1800 * 128 * 512
+    n4 = 128 * 512 * 512 * 10
+    state = (2 * nf + 2 * ng + 4 * n4) * 4
+    scratch = 180 * 128 * 512 * 16 * 4
+    assert state + scratch <= b <= state + scratch + 64 * 2 ** 20
+
+
+def test_null_handles():
+    L = rt4d.lib()
+    assert L.rt_forward(None, None, None, None) == rt4d.RT_E_ARG
+    assert L.rt_job_step(None, 1, None) == rt4d.RT_E_ARG
+    L.rt_plan_destroy(None)
+    L.rt_job_destroy(None)

@@ -1,0 +1,225 @@
+"""GPU parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances: tables bit-exact; operators rel-L2 <= 1e-5 (FP32 arithmetic
+against FP64); TV operators <= 1e-6; reconstructions after a fixed iteration
+count rel-L2 <= 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1809_09725_amd import inputs, rt4d
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def og(G):
+    return O.Geom(**G.__dict__)
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(DEV)
+
+
+C1 = rt4d.Geom(N=64, Nz=1, Ns=64, Ntheta=720, Npi=8, K=8, Nt=8)
+SHAPES = [
+    C1,
+    rt4d.Geom(N=45, Nz=3, Ns=50, Ntheta=3 * 37, Npi=3, K=5, Nt=3),     # ragged, K % 4 != 0
+    rt4d.Geom(N=70, Nz=2, Ns=70, Ntheta=4 * 25, Npi=4, K=12, Nt=4),    # two channel chunks
+    rt4d.Geom(N=33, Nz=2, Ns=40, Ntheta=2 * 45, Npi=2, K=16, Nt=2),
+    rt4d.Geom(N=40, Nz=1, Ns=31, Ntheta=12, Npi=1, K=1, Nt=1),         # static, K = 1
+    rt4d.Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1),            # one ray
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch.cuda.set_device(DEV)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_tables_bit_exact():
+    for G in (C1, SHAPES[1]):
+        p = rt4d.Plan(G)
+        got = p.tables()
+        want = O.tables(og(G))
+        for k in ("theta", "t", "cls", "rot", "flip"):
+            assert np.array_equal(got[k], want[k]), k
+
+
+@pytest.mark.parametrize("G", SHAPES, ids=lambda G: f"N{G.N}z{G.Nz}s{G.Ns}t{G.Ntheta}k{G.K}")
+def test_forward_adjoint_parity(G):
+    print(f"case {G}", flush=True)
+    p = rt4d.Plan(G)
+    for seed, maker in ((11, "uniform"), (12, "smooth")):
+        if maker == "uniform":
+            f = inputs.uniform(G.f_shape, seed)
+        else:
+            f = inputs.smooth_coeffs(G.N, G.Nz, G.K, seed)
+        s = inputs.uniform(G.g_shape, seed + 100)
+        Rf = p.forward(T(f)).cpu().numpy()
+        Rs = p.adjoint(T(s)).cpu().numpy()
+        e_f = rel(Rf, O.forward(og(G), f))
+        e_a = rel(Rs, O.adjoint(og(G), s))
+        print(f"  {maker}: forward {e_f:.2e} adjoint {e_a:.2e}")
+        assert e_f <= 1e-5 and e_a <= 1e-5
+
+
+def test_adjoint_identity_on_gpu():
+    G = SHAPES[2]
+    p = rt4d.Plan(G)
+    f = T(inputs.uniform(G.f_shape, 3))
+    s = T(inputs.uniform(G.g_shape, 4))
+    Rf, Rs = p.forward(f), p.adjoint(s)
+    lhs, rhs = rt4d.rt_dot(Rf, s), rt4d.rt_dot(f, Rs)
+    scale = np.sqrt(rt4d.rt_dot(Rf, Rf) * rt4d.rt_dot(s, s))
+    assert abs(lhs - rhs) <= 2e-6 * scale
+
+
+def test_rt_dot_fp64():
+    x = torch.rand(1_000_003, device=DEV) - 0.5
+    y = torch.rand(1_000_003, device=DEV) - 0.5
+    want = float(np.dot(x.cpu().double().numpy(), y.cpu().double().numpy()))
+    assert abs(rt4d.rt_dot(x, y) - want) <= 1e-12 * abs(want) + 1e-12
+    assert rt4d.rt_dot(x[:0], y[:0]) == 0.0
+
+
+@pytest.mark.parametrize("G", [SHAPES[1], SHAPES[2], rt4d.Geom(N=20, Nz=4, Ns=20, Ntheta=60, Npi=6, K=32, Nt=5),
+                               rt4d.Geom(N=9, Nz=1, Ns=9, Ntheta=8, Npi=8, K=3, Nt=1)],
+                         ids=lambda G: f"N{G.N}z{G.Nz}k{G.K}t{G.Nt}")
+def test_tv_parity(G):
+    p = rt4d.Plan(G)
+    lam1, lam2 = 0.3, 2.5
+    f = inputs.uniform(G.f_shape, 5)
+    q = inputs.uniform(G.p_shape, 6)
+    pg = p.tv_grad(T(f), lam2).cpu().numpy()
+    assert rel(pg, O.tv_grad(og(G), f, lam2)) <= 1e-6
+    dv = p.tv_div(T(q), lam2).cpu().numpy()
+    assert rel(dv, O.tv_div(og(G), q, lam2)) <= 1e-6
+    sh = p.shrink(T(q), lam1).cpu().numpy()
+    assert rel(sh, O.shrink(q, lam1)) <= 1e-6
+    assert np.abs(p.shrink(T(q), 0.0).cpu().numpy()).max() == 0.0
+
+
+def test_solve_parity_c1():
+    """C1 workload: moving ellipses, 50 iterations, explicit steps."""
+    G = C1
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 3, seed=1, axis_range=(2, 8), rho_range=(0.5, 1.0),
+                             speed_per_halfturn=1.0)
+    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=1).numpy()
+    p = rt4d.Plan(G)
+    L = O.power(og(G), n_pow=20, seed=9)
+    lam1 = 2.0 ** -9 * L * L
+    kw = dict(lambda1=lam1, lambda2=4.0, n_iter=50, tau=0.9 / L, sigma=0.9 / L)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, **kw)
+    fo, ro = O.solve(og(G), g, route="folded", **kw)
+    e = rel(f.cpu().numpy(), fo)
+    print(f"C1 solve rel {e:.2e}, objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
+    assert e <= 1e-3
+    assert abs(rep["objective"] - ro["objective"]) <= 1e-4 * abs(ro["objective"])
+    assert rep["iters_done"] == 50
+
+
+def test_step_rule_power_iteration():
+    G = SHAPES[1]
+    p = rt4d.Plan(G)
+    g = inputs.uniform(G.g_shape, 8)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, lambda1=0.01, lambda2=1.0, n_iter=2, n_pow=20, seed=77)
+    _, ro = O.solve(og(G), g, lambda1=0.01, lambda2=1.0, n_iter=2, n_pow=20, seed=77)
+    assert abs(rep["L_R"] - ro["L_R"]) <= 1e-5 * ro["L_R"]
+    assert abs(rep["L_G"] - ro["L_G"]) <= 1e-12 * ro["L_G"]
+    assert abs(rep["tau"] - ro["tau"]) <= 1e-5 * ro["tau"]
+
+
+def test_solve_monitors_and_tolerance():
+    G = SHAPES[1]
+    p = rt4d.Plan(G)
+    g = inputs.uniform(G.g_shape, 8)
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=30, tau=0.05, sigma=0.05, check_every=5)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, **kw)
+    fo, ro = O.solve(og(G), g, **kw)
+    assert rel(f.cpu().numpy(), fo) <= 1e-4
+    assert abs(rep["rel_change"] - ro["rel_change"]) <= 1e-3 * ro["rel_change"]
+    assert abs(rep["residual"] - ro["residual"]) <= 1e-5 * ro["residual"]
+    kw.update(n_iter=1000, check_every=1, tol=1e-3)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, **kw)
+    _, ro = O.solve(og(G), g, **kw)
+    assert abs(rep["iters_done"] - ro["iters_done"]) <= 1
+
+
+def test_deterministic_bitwise():
+    G = SHAPES[2]
+    p = rt4d.Plan(G)
+    f = T(inputs.uniform(G.f_shape, 21))
+    s = T(inputs.uniform(G.g_shape, 22))
+    assert torch.equal(p.forward(f), p.forward(f))
+    assert torch.equal(p.adjoint(s), p.adjoint(s))
+    a = torch.zeros(G.f_shape, device=DEV)
+    b = torch.zeros(G.f_shape, device=DEV)
+    r1 = p.solve(s, a, lambda1=0.1, lambda2=2.0, n_iter=7, check_every=7)
+    r2 = p.solve(s, b, lambda1=0.1, lambda2=2.0, n_iter=7, check_every=7)
+    assert torch.equal(a, b) and r1 == r2
+
+
+def test_empty_and_errors():
+    G = rt4d.Geom(N=16, Nz=0, Ns=16, Ntheta=16, Npi=2, K=4, Nt=2)
+    p = rt4d.Plan(G)
+    f = torch.zeros(G.f_shape, device=DEV)
+    g = torch.zeros(G.g_shape, device=DEV)
+    p.forward(f, g)
+    p.adjoint(g, f)
+    rep = p.solve(g, f, lambda1=0.1, lambda2=1.0, n_iter=3, tau=0.1, sigma=0.1)
+    assert rep["iters_done"] == 3 and rep["residual"] == 0.0
+    G = SHAPES[1]
+    p = rt4d.Plan(G)
+    f = torch.zeros(G.f_shape, device=DEV)
+    with pytest.raises(ValueError):
+        p.forward(f[:, :, :, :-1])
+    big = torch.zeros(G.f_shape[0] * G.f_shape[1] * G.f_shape[2] * G.f_shape[3] + 1, device=DEV)
+    g = torch.zeros(G.g_shape, device=DEV)
+    with pytest.raises(rt4d.RtError) as ei:   # 4-byte offset: not 16-byte aligned
+        rt4d.lib()
+        rc = rt4d.lib().rt_forward(p.h, rt4d.ctypes.c_void_p(big.data_ptr() + 4),
+                                   rt4d.ctypes.c_void_p(g.data_ptr()), None)
+        rt4d._check(rc)
+    assert ei.value.code == rt4d.RT_E_ARG
+    with pytest.raises(rt4d.RtError):
+        p.solve(g, f, lambda1=-1.0, lambda2=1.0, n_iter=1)
+    with pytest.raises(rt4d.RtError):
+        p.shrink(torch.zeros(G.p_shape, device=DEV), -0.5)
+
+
+def test_checkpoint_resume_bitwise():
+    G = SHAPES[1]
+    p = rt4d.Plan(G)
+    g = T(inputs.uniform(G.g_shape, 31))
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=50, tau=0.05, sigma=0.05)
+    fa = torch.zeros(G.f_shape, device=DEV)
+    ja = rt4d.Job(p, g, fa, **kw)
+    ja.step(50)
+    fb = torch.zeros(G.f_shape, device=DEV)
+    jb = rt4d.Job(p, g, fb, **kw)
+    jb.step(25)
+    ck = jb.checkpoint()
+    jb.close()
+    fc = torch.full(G.f_shape, 3.0, device=DEV)
+    jc = rt4d.Job(p, g, fc, **kw)
+    jc.restore(ck)
+    assert jc.iters == 25
+    jc.step(100)
+    assert jc.done and jc.iters == 50
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fc)
