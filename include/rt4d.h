@@ -31,7 +31,8 @@
  * memory of the current device, "host" = ordinary host memory):
  *   f   [Nz][N][N][K]       coefficient volumes f_k, basis index innermost
  *   g   [Ntheta][Nz][Ns]    sinogram
- *   p   [Nz][N][N][Nt][4]   4D gradient / dual field, components (x, y, z, t)
+ *   p   [Nz][Nt][4][N][N]   4D gradient / dual field: for each slice and time
+ *                           frame, four component planes (x, y, z, t)
  *
  * Conventions for every call:
  *   - the caller owns every array passed in; the library never frees them;

@@ -57,6 +57,7 @@ struct FwdCfg {
     int nbt = 1;          // bin tiles
     int stride = 4;       // floats per staged position (KC + padding)
     int vec = 1;          // 4: float4 staging loads
+    int pf = 4;           // float4 per thread that hold one staged line (4 or 8)
     size_t lds = 0;       // bytes of LDS per workgroup
 };
 
@@ -90,6 +91,7 @@ struct Plan {
     int *d_gcls = nullptr;      // [ngroups][A], -1 = empty slot
     int *d_gwalk = nullptr;     // [ngroups]
     float *d_scr = nullptr;     // [Ntheta0][Nz][Ns][K]: P (forward), g~ (adjoint)
+    float *d_frames = nullptr;  // [Nz][Nt][N][N]: time frames for tv_grad / tv_norm
     double *d_part = nullptr;   // FP64 partial sums
     size_t part_cap = 0;        // doubles in d_part
     double *d_red = nullptr;    // final FP64 sums (16 doubles)
@@ -103,7 +105,8 @@ struct Job {
     float *f = nullptr;
     float *ft = nullptr;        // extrapolated primal f~
     float *h1 = nullptr;        // dual of the data term, sinogram shaped
-    float *h2 = nullptr;        // dual of the TV term, [Nz][N][N][Nt][4]
+    float *h2 = nullptr;        // dual of the TV term, [Nz][Nt][4][N][N]
+    float *Ff = nullptr;        // time frames of f~, [Nz][Nt][N][N]
     float *work = nullptr;      // R_T* h1, coefficient shaped
     float *sino = nullptr;      // R_T f for the report, sinogram shaped
     double tau = 0, sigma = 0, L_R = 0, L_G = 0;
@@ -136,12 +139,15 @@ unsigned voxel_blocks(const rt_geom &g);  // workgroups (= partials) of the voxe
 int launch_tv_grad(const Plan &p, const float *f, float lambda2, float *pout, hipStream_t s);
 int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hipStream_t s);
 int launch_shrink(const Plan &p, float *pio, float lambda1, size_t n4, hipStream_t s);
-// h2 <- shrink(h2 + sigma grad S f~); FP64 partial sum of |grad S f~| per block
-int launch_grad_shrink(const Plan &p, const float *ft, float *h2, float sigma, float lambda1,
+// F = S f (time frames, planar)
+int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s);
+// h2 <- shrink(h2 + sigma grad F), F = S f~; FP64 partial sum of |grad F| per block
+int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
                        float lambda2, double *part, hipStream_t s);
-// f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; partials |f+ - f|^2, |f+|^2
+// f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; Ff = S f~;
+// partials |f+ - f|^2, |f+|^2
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
-                      float tau, float lambda2, double *part, hipStream_t s);
+                      float *Ff, float tau, float lambda2, double *part, hipStream_t s);
 // sum over voxels and frames of |grad S f| (FP64 partials)
 int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s);
 

@@ -61,7 +61,7 @@ size_t plan_scratch_bytes(const rt_geom &g)
 
 size_t job_state_bytes(const rt_geom &g)
 {
-    return (2 * nf_of(g) + 2 * ng_of(g) + 4 * n4_of(g)) * sizeof(float);
+    return (2 * nf_of(g) + 2 * ng_of(g) + 5 * n4_of(g)) * sizeof(float);
 }
 
 // Sec. 4, eq. discrt: theta_i = i*pi/Ntheta0, t_i = i/Ntheta (theta = alpha t,
@@ -126,7 +126,7 @@ static int configure(Plan &p)
     for (int a = 0; a < n0; ++a)
         (std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? rows : cols).push_back(a);
     FwdCfg &F = p.fwd;
-    const int pairs_max = 256 * 8;
+    const int pairs_max = 512 * 4;   // 512 threads x 4 rays
     F.BT = std::min(g.Ns, pairs_max);
     F.nbt = (g.Ns + F.BT - 1) / F.BT;
     F.A = std::max(1, pairs_max / F.BT);
@@ -141,11 +141,22 @@ static int configure(Plan &p)
         }
     }
     F.ngroups = (int)gwalk.size();
-    if (pick_kc(g.K, g.N + 2, budget, &F.KC, &F.stride))
-        return fail(RT_E_SHAPE, "N=%d too large for the projector's staging buffer", g.N);
+    // two LDS line buffers; one line must fit the 512 threads' prefetch registers
+    F.KC = 0;
+    const int K4 = (g.K + 3) / 4 * 4;
+    for (int kc : {16, 8, 4}) {
+        if (F.KC || (kc > K4 && kc != 4) || g.N * kc > 4 * 8 * 512) continue;
+        for (int pad : {4, 0})
+            if (!F.KC && 2 * (size_t)(g.N + 2) * (kc + pad) * sizeof(float) <= 160 * 1024) {
+                F.KC = kc;
+                F.stride = kc + pad;
+            }
+    }
+    if (!F.KC) return fail(RT_E_SHAPE, "N=%d too large for the projector's staging buffer", g.N);
+    F.pf = g.N * F.KC <= 4 * 4 * 512 ? 4 : 8;
     F.nkc = (g.K + F.KC - 1) / F.KC;
     F.vec = (g.K % 4 == 0) ? 4 : 1;
-    F.lds = (size_t)(g.N + 2) * F.stride * sizeof(float);
+    F.lds = 2 * (size_t)(g.N + 2) * F.stride * sizeof(float);
 
     // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
     AdjCfg &B = p.adj;
@@ -178,7 +189,8 @@ static int configure(Plan &p)
 static void free_plan(Plan &p)
 {
     for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
-                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_scr, (void *)p.d_part,
+                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_scr, (void *)p.d_frames,
+                      (void *)p.d_part,
                       (void *)p.d_red})
         if (ptr) (void)hipFree(ptr);
 }
@@ -212,6 +224,9 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     const size_t scr = std::max<size_t>(plan_scratch_bytes(p.g), 256);
     RT_HIP(hipMalloc(&p.d_scr, scr));
     p.bytes += scr;
+    const size_t frb = std::max<size_t>(n4_of(p.g), 1) * sizeof(float);
+    RT_HIP(hipMalloc(&p.d_frames, frb));
+    p.bytes += frb;
     p.part_cap = (size_t)1 << 18;
     RT_HIP(hipMalloc(&p.d_part, p.part_cap * sizeof(double)));
     RT_HIP(hipMalloc(&p.d_red, 16 * sizeof(double)));

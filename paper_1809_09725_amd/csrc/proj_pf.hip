@@ -26,14 +26,79 @@
 namespace rt {
 namespace {
 
-template <int KC, int PPT, int VEC>
-__global__ __launch_bounds__(NT, 2) void k_project(
+constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
+
+// Staging of one line (row or column of a slice, KC channels, positions
+// 0..N-1 into LDS slots 1..N) through registers: the loads of line l+1 are
+// issued before the taps of line l are summed, and written to the other LDS
+// buffer afterwards.  PF float4 per thread cover a whole line
+// (N * KC <= 4 * PF * FT).  VEC = 4: float4 loads (K % 4 == 0); VEC = 1:
+// scalar loads of the same PF*4 values.
+template <int KC, int PF, int VEC>
+struct LinePrefetch {
+    float4 r[PF];
+    __device__ inline void load(const float *__restrict__ src, size_t pstep, int N, int k0, int K)
+    {
+        if (VEC == 4) {
+            constexpr int NQ = KC / 4;
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int e = threadIdx.x + FT * j;
+                const int pos = e / NQ, kq = e % NQ;
+                r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (pos < N && k0 + 4 * kq < K) r[j] = *(const float4 *)(src + (size_t)pos * pstep + 4 * kq);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = threadIdx.x + FT * (4 * j + i);
+                    const int pos = e / KC, kk = e % KC;
+                    v[i] = (pos < N && k0 + kk < K) ? src[(size_t)pos * pstep + kk] : 0.f;
+                }
+                r[j] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    }
+    __device__ inline void store(float *__restrict__ buf, int N, int stride) const
+    {
+        if (VEC == 4) {
+            constexpr int NQ = KC / 4;
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int e = threadIdx.x + FT * j;
+                const int pos = e / NQ, kq = e % NQ;
+                if (pos < N) *(float4 *)(buf + (pos + 1) * stride + 4 * kq) = r[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const float v[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = threadIdx.x + FT * (4 * j + i);
+                    const int pos = e / KC, kk = e % KC;
+                    if (pos < N) buf[(pos + 1) * stride + kk] = v[i];
+                }
+            }
+        }
+    }
+};
+
+// Joseph's ray-driven projection of KC channels of slice z for the rays
+// (class, bin) of one group; P(a,z,b,k0..k0+KC) = sum over lines of the
+// linear interpolation between the two positions around the ray, times the
+// line spacing along the ray 1/c.
+template <int KC, int PPT, int PF, int VEC>
+__global__ __launch_bounds__(FT) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
     int nbt, int nkc, int stride, unsigned nblocks)
 {
-    extern __shared__ float line[];   // [N + 2 positions][stride], positions -1 .. N
+    extern __shared__ float lines[];   // 2 buffers x [N + 2 slots][stride], slots = positions -1 .. N
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
     lid /= nbt;
@@ -45,22 +110,20 @@ __global__ __launch_bounds__(NT, 2) void k_project(
     const int walk = gwalk[grp];
     const int k0 = kc * KC;
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
+    const int bufsz = (N + 2) * stride;
 
     double base[PPT], slope[PPT];
     float invc[PPT];
-    int cls[PPT], bin[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int pr = tid + NT * j;
+        const int pr = tid + FT * j;
         const int slot = pr / BT;
         const int b = bt * BT + pr % BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
-        cls[j] = (a >= 0 && b < Ns) ? a : -1;
-        bin[j] = b;
         base[j] = -1.0e9;   // far outside: both taps get weight 0
         slope[j] = 0.0;
         invc[j] = 0.f;
-        if (cls[j] >= 0) {
+        if (a >= 0 && b < Ns) {
             const double cs = ccos[a], sn = csin[a], sb = (double)b - hS;
             if (walk == 0) {   // |cos| >= |sin|: the ray crosses every row once
                 base[j] = sb / cs + hN;
@@ -80,31 +143,24 @@ __global__ __launch_bounds__(NT, 2) void k_project(
 #pragma unroll
         for (int k = 0; k < KC; ++k) acc[j][k] = 0.f;
 
-    for (int e = tid; e < 2 * stride; e += NT)   // zero positions -1 and N
-        line[(e < stride ? 0 : (N + 1) * stride) + e % stride] = 0.f;
+    for (int e = tid; e < 4 * stride; e += FT) {   // zero slots -1 and N of both buffers
+        const int b = e / (2 * stride), w = e % (2 * stride);
+        lines[b * bufsz + (w < stride ? 0 : (N + 1) * stride) + w % stride] = 0.f;
+    }
 
-    const size_t zoff = (size_t)z * N * N * K;
+    const size_t zoff = (size_t)z * N * N * K + k0;
     const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;   // next line
     const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;   // next position
 
+    LinePrefetch<KC, PF, VEC> pf;
+    pf.load(f + zoff, pstep, N, k0, K);
+    pf.store(lines, N, stride);
+    __syncthreads();
+
     for (int l = 0; l < N; ++l) {
-        __syncthreads();
-        const float *src = f + zoff + (size_t)l * lstep + k0;
-        if (VEC == 4) {
-            constexpr int NQ = KC / 4;
-            for (int e = tid; e < N * NQ; e += NT) {
-                const int pos = e / NQ, kq = e % NQ;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (k0 + 4 * kq < K) v = *(const float4 *)(src + (size_t)pos * pstep + 4 * kq);
-                *(float4 *)(line + (pos + 1) * stride + 4 * kq) = v;
-            }
-        } else {
-            for (int e = tid; e < N * KC; e += NT) {
-                const int pos = e / KC, kk = e % KC;
-                line[(pos + 1) * stride + kk] = (k0 + kk < K) ? src[(size_t)pos * pstep + kk] : 0.f;
-            }
-        }
-        __syncthreads();
+        const bool more = l + 1 < N;
+        if (more) pf.load(f + zoff + (size_t)(l + 1) * lstep, pstep, N, k0, K);
+        const float *line = lines + (l & 1) * bufsz;
         const double lc = (double)l - hN;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -112,7 +168,7 @@ __global__ __launch_bounds__(NT, 2) void k_project(
             const double fl = floor(u);
             const int q0 = (int)fl;
             const float fr = (float)(u - fl);
-            const bool in = (q0 >= -1) && (q0 < N);
+            const bool in = (unsigned)(q0 + 1) <= (unsigned)N;   // -1 <= q0 <= N-1
             const float w1 = in ? fr * invc[j] : 0.f;
             const float w0 = in ? (1.f - fr) * invc[j] : 0.f;
             const float *t0 = line + (in ? q0 + 1 : 0) * stride;
@@ -125,13 +181,23 @@ __global__ __launch_bounds__(NT, 2) void k_project(
                 acc[j][k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, acc[j][k + 2]));
                 acc[j][k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, acc[j][k + 3]));
             }
+            // finish this ray's FMAs before the next ray's tap loads are issued:
+            // hoisting the loads of all rays needs 32 VGPRs per ray and spills
+#pragma unroll
+            for (int k = 0; k < KC; ++k) asm volatile("" : "+v"(acc[j][k])::"memory");
         }
+        if (more) pf.store(lines + ((l + 1) & 1) * bufsz, N, stride);
+        __syncthreads();
     }
 
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        if (cls[j] < 0) continue;
-        float *dst = P + (((size_t)cls[j] * Nz + z) * Ns + bin[j]) * K + k0;
+        const int pr = tid + FT * j;
+        const int slot = pr / BT;
+        const int b = bt * BT + pr % BT;
+        const int a = slot < A ? gcls[grp * A + slot] : -1;
+        if (a < 0 || b >= Ns) continue;
+        float *dst = P + (((size_t)a * Nz + z) * Ns + b) * K + k0;
 #pragma unroll
         for (int k = 0; k < KC; ++k)
             if (k0 + k < K) dst[k] = acc[j][k];
@@ -333,27 +399,41 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     }
 }
 
-template <int KC, int PPT, int VEC>
-static void launch_project_t(const Plan &p, const float *f, hipStream_t s, unsigned nb)
+template <int KC, int PPT, int PF, int VEC>
+static int launch_project_t(const Plan &p, const float *f, hipStream_t s, unsigned nb)
 {
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
+    auto kern = k_project<KC, PPT, PF, VEC>;
+    static bool attr = false;   // raise the dynamic LDS limit once per instantiation
+    if (!attr) {
+        RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        attr = true;
+    }
     KTimer kt("k_project", s);
-    hipLaunchKernelGGL((k_project<KC, PPT, VEC>), dim3(nb), dim3(NT), F.lds, s, f, p.d_scr,
-                       p.d_gcls, p.d_gwalk, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A,
-                       F.ngroups, F.BT, F.nbt, F.nkc, F.stride, nb);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(FT), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
+                       p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
+                       F.nkc, F.stride, nb);
     kt.stop();
+    return RT_OK;
+}
+
+template <int KC, int PF, int VEC>
+static int launch_project_p(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
+{
+    switch (ppt) {
+    case 1: return launch_project_t<KC, 1, PF, VEC>(p, f, s, nb);
+    case 2: return launch_project_t<KC, 2, PF, VEC>(p, f, s, nb);
+    default: return launch_project_t<KC, 4, PF, VEC>(p, f, s, nb);
+    }
 }
 
 template <int KC, int VEC>
-static void launch_project_kv(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
+static int launch_project_k(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
 {
-    switch (ppt) {
-    case 1: launch_project_t<KC, 1, VEC>(p, f, s, nb); break;
-    case 2: launch_project_t<KC, 2, VEC>(p, f, s, nb); break;
-    case 4: launch_project_t<KC, 4, VEC>(p, f, s, nb); break;
-    default: launch_project_t<KC, 8, VEC>(p, f, s, nb); break;
-    }
+    return p.fwd.pf <= 4 ? launch_project_p<KC, 4, VEC>(p, f, s, nb, ppt)
+                         : launch_project_p<KC, 8, VEC>(p, f, s, nb, ppt);
 }
 
 template <int KC, int VEC>
@@ -379,21 +459,23 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     const FwdCfg &F = p.fwd;
     if (G.Nz == 0) return RT_OK;
     const int pairs = F.A * F.BT;
-    const int ppt = pairs <= NT ? 1 : pairs <= 2 * NT ? 2 : pairs <= 4 * NT ? 4 : 8;
+    const int ppt = pairs <= FT ? 1 : pairs <= 2 * FT ? 2 : 4;
     const unsigned nb = (unsigned)G.Nz * F.ngroups * F.nkc * F.nbt;
+    int rc;
     if (F.vec == 4) {
         switch (F.KC) {
-        case 4: launch_project_kv<4, 4>(p, f, s, nb, ppt); break;
-        case 8: launch_project_kv<8, 4>(p, f, s, nb, ppt); break;
-        default: launch_project_kv<16, 4>(p, f, s, nb, ppt); break;
+        case 4: rc = launch_project_k<4, 4>(p, f, s, nb, ppt); break;
+        case 8: rc = launch_project_k<8, 4>(p, f, s, nb, ppt); break;
+        default: rc = launch_project_k<16, 4>(p, f, s, nb, ppt); break;
         }
     } else {
         switch (F.KC) {
-        case 4: launch_project_kv<4, 1>(p, f, s, nb, ppt); break;
-        case 8: launch_project_kv<8, 1>(p, f, s, nb, ppt); break;
-        default: launch_project_kv<16, 1>(p, f, s, nb, ppt); break;
+        case 4: rc = launch_project_k<4, 1>(p, f, s, nb, ppt); break;
+        case 8: rc = launch_project_k<8, 1>(p, f, s, nb, ppt); break;
+        default: rc = launch_project_k<16, 1>(p, f, s, nb, ppt); break;
         }
     }
+    if (rc) return rc;
     RT_HIP(hipGetLastError());
     const unsigned nbc = row_blocks((long)G.Ntheta * G.Nz);
     float *o = mode == CONTRACT_STORE ? g : h1;

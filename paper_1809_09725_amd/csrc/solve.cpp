@@ -89,9 +89,10 @@ int power_iteration(Job &J, hipStream_t s)
 
 void free_job(Job &J)
 {
-    for (void *ptr : {(void *)J.ft, (void *)J.work, (void *)J.h1, (void *)J.sino, (void *)J.h2})
+    for (void *ptr : {(void *)J.ft, (void *)J.work, (void *)J.h1, (void *)J.sino, (void *)J.h2,
+                      (void *)J.Ff})
         if (ptr) (void)hipFree(ptr);
-    J.ft = J.work = J.h1 = J.sino = J.h2 = nullptr;
+    J.ft = J.work = J.h1 = J.sino = J.h2 = J.Ff = nullptr;
 }
 
 int alloc_job(Job &J)
@@ -104,7 +105,8 @@ int alloc_job(Job &J)
     RT_HIP(hipMalloc(&J.h1, ng * sizeof(float)));
     RT_HIP(hipMalloc(&J.sino, ng * sizeof(float)));
     RT_HIP(hipMalloc(&J.h2, 4 * n4 * sizeof(float)));
-    J.bytes = (2 * nf + 2 * ng + 4 * n4) * sizeof(float);
+    RT_HIP(hipMalloc(&J.Ff, n4 * sizeof(float)));
+    J.bytes = (2 * nf + 2 * ng + 5 * n4) * sizeof(float);
     return RT_OK;
 }
 
@@ -163,8 +165,9 @@ int create_job(const rt_plan *plan, const rt_solve_params *prm, const float *g, 
             J.tau = J.sigma = 1.0 / L;
         }
     }
-    // f~ = f, h1 = 0, h2 = 0
+    // f~ = f, h1 = 0, h2 = 0, frames of f~
     if (!rc) rc = launch_copy(J.ft, f, nf_of(p.g), s);
+    if (!rc) rc = launch_frames(p, J.ft, J.Ff, s);
     if (!rc) rc = launch_fill(J.h1, 0.f, ng_of(p.g), s);
     if (!rc) rc = launch_fill(J.h2, 0.f, 4 * n4_of(p.g), s);
     if (rc) {
@@ -192,10 +195,10 @@ int step_job(Job &J, int n, hipStream_t s)
         // step 3: h1 <- (h1 + sigma (R_T f~ - g)) / (1 + sigma)
         if ((rc = launch_forward_pf(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
         // step 4: h2 <- shrink(h2 + sigma grad S f~)
-        if ((rc = launch_grad_shrink(p, J.ft, J.h2, sigma, l1, l2, pg, s))) return rc;
+        if ((rc = launch_grad_shrink(p, J.Ff, J.h2, sigma, l1, l2, pg, s))) return rc;
         // steps 5-6: f+ = f - tau R_T* h1 + tau S^T div h2, f~ = 2 f+ - f
         if ((rc = launch_adjoint_pf(p, J.h1, J.work, s))) return rc;
-        if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, tau, l2, pd, s))) return rc;
+        if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s))) return rc;
         ++J.iters;
         if (check && p.g.Nz > 0) {
             const int nbv = (int)voxel_blocks(p.g);
@@ -261,7 +264,7 @@ extern "C" int rt_job_bytes(const rt_geom *geom, rt_form, rt_prec, size_t *bytes
     const size_t tables = ((size_t)g.Ntheta * g.K + (size_t)g.Nt * g.K) * sizeof(float) +
                           (size_t)(g.Ntheta / g.Npi) * 2 * sizeof(double) + 64 * 1024;
     const size_t parts = ((size_t)1 << 18) * sizeof(double) + 16 * sizeof(double);
-    *bytes = tables + parts + plan_scratch_bytes(g) + job_state_bytes(g);
+    *bytes = tables + parts + plan_scratch_bytes(g) + n4_of(g) * sizeof(float) + job_state_bytes(g);
     return RT_OK;
 }
 
@@ -347,6 +350,8 @@ extern "C" int rt_job_restore(rt_job *job, const void *host_buf, void *stream)
     if (nf) RT_HIP(hipMemcpyAsync(J.ft, b + nf, nf, hipMemcpyHostToDevice, s));
     if (ng) RT_HIP(hipMemcpyAsync(J.h1, b + 2 * nf, ng, hipMemcpyHostToDevice, s));
     if (n4) RT_HIP(hipMemcpyAsync(J.h2, b + 2 * nf + ng, n4, hipMemcpyHostToDevice, s));
+    int rc = launch_frames(*J.plan, J.ft, J.Ff, s);   // frames are a function of f~
+    if (rc) return rc;
     RT_HIP(hipStreamSynchronize(s));
     J.iters = h.iters;
     J.stopped = h.stopped != 0;

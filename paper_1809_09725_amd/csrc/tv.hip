@@ -7,52 +7,60 @@
 //          rows of the discrete TV literature, lambda2 on the time axis
 //   shrink the prox of sigma F2* (Sec. 3): p / max(1, |p|_2 / lambda1)
 //
-// One thread per voxel; the K coefficients of a voxel are 4*K contiguous
-// bytes, its Nt*4 dual values 16*Nt contiguous bytes, so every access is a
-// coalesced row of the volume.  These kernels are bound by HBM bandwidth.
+// Layouts: f is [Nz][N][N][K] (basis index innermost, as the projector wants
+// it); the frames F [Nz][Nt][N][N] and the dual p [Nz][Nt][4][N][N] are
+// component planes, so one thread per voxel reads and writes whole coalesced
+// rows.  The K-innermost rows of f go through LDS: a workgroup of 256
+// consecutive voxels loads (or stores) its 256*K values as contiguous float4,
+// and each thread works on its own voxel from LDS.  All kernels here are
+// bound by HBM bandwidth.
 #include "common.h"
 #include "internal.h"
 
 namespace rt {
 namespace {
 
+// LDS row stride (floats) of one voxel's K values: odd, so that 32
+// consecutive voxels read with ds_read_b32 hit 32 different banks.
+__host__ __device__ constexpr int kstride(int KT) { return KT + 1; }
+
+// Cooperative copy of voxels [v0, v0 + nv) x K floats from global
+// (contiguous) to LDS rows of stride KS.
 template <int KT>
-__device__ inline void load_k(const float *__restrict__ src, int K, float (&c)[KT])
+__device__ inline void f_to_lds(const float *__restrict__ src, size_t v0, int nv, int K,
+                                float *__restrict__ lds)
 {
+    constexpr int KS = kstride(KT);
+    const float *base = src + v0 * K;
+    const int n = nv * K;
     if ((K & 3) == 0) {
-#pragma unroll
-        for (int k = 0; k < KT; k += 4) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < K) v = *(const float4 *)(src + k);
-            c[k] = v.x; c[k + 1] = v.y; c[k + 2] = v.z; c[k + 3] = v.w;
+        for (int e = threadIdx.x * 4; e < n; e += NT * 4) {
+            const float4 x = *(const float4 *)(base + e);
+            const int v = e / K, k = e % K;
+            float *d = lds + v * KS + k;
+            d[0] = x.x; d[1] = x.y; d[2] = x.z; d[3] = x.w;
         }
     } else {
-#pragma unroll
-        for (int k = 0; k < KT; ++k) c[k] = k < K ? src[k] : 0.f;
+        for (int e = threadIdx.x; e < n; e += NT) lds[(e / K) * KS + e % K] = base[e];
     }
 }
 
 template <int KT>
-__device__ inline void store_k(float *__restrict__ dst, int K, const float (&c)[KT])
+__device__ inline void lds_to_f(const float *__restrict__ lds, size_t v0, int nv, int K,
+                                float *__restrict__ dst)
 {
+    constexpr int KS = kstride(KT);
+    float *base = dst + v0 * K;
+    const int n = nv * K;
     if ((K & 3) == 0) {
-#pragma unroll
-        for (int k = 0; k < KT; k += 4)
-            if (k < K) *(float4 *)(dst + k) = make_float4(c[k], c[k + 1], c[k + 2], c[k + 3]);
+        for (int e = threadIdx.x * 4; e < n; e += NT * 4) {
+            const int v = e / K, k = e % K;
+            const float *s = lds + v * KS + k;
+            *(float4 *)(base + e) = make_float4(s[0], s[1], s[2], s[3]);
+        }
     } else {
-#pragma unroll
-        for (int k = 0; k < KT; ++k)
-            if (k < K) dst[k] = c[k];
+        for (int e = threadIdx.x; e < n; e += NT) base[e] = lds[(e / K) * KS + e % K];
     }
-}
-
-template <int KT>
-__device__ inline float frame(const float *__restrict__ Srow, const float (&c)[KT])
-{
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) s = fmaf(Srow[k], c[k], s);
-    return s;
 }
 
 // S into LDS as [Nt][KT], zero padded.
@@ -63,59 +71,96 @@ __device__ inline void stage_S(const float *__restrict__ S, int K, int Nt, float
         const int m = e / KT, k = e % KT;
         sS[e] = k < K ? S[m * K + k] : 0.f;
     }
-    __syncthreads();
 }
 
-// MODE 0: p = grad f~ (store).  MODE 1: h2 <- shrink(h2 + sigma grad f~).
-// MODE 2: only the partial sum of |grad f| (no store).
-// With part != NULL each workgroup writes the FP64 sum of |grad f~| over its voxels.
-template <int KT, int MODE>
-__global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ f,
-                                             const float *__restrict__ S, float lambda2,
-                                             float sigma, float lambda1, float *__restrict__ p,
-                                             double *__restrict__ part, int N, int Nz, int K,
-                                             int Nt)
+// F[z][m][pv] = sum_k S[m][k] f_k(v) from the LDS row of voxel v.
+template <int KT>
+__device__ inline void write_frames(const float *__restrict__ row, const float *__restrict__ sS,
+                                    float *__restrict__ F, size_t v, size_t plane, int Nt)
 {
-    extern __shared__ float sS[];
-    __shared__ double sh[NT / 64];
+    float c[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) c[k] = row[k];
+    const size_t z = v / plane, pv = v % plane;
+    float *Fz = F + z * Nt * plane + pv;
+    for (int m = 0; m < Nt; ++m) {
+        const float *Sm = sS + m * KT;
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) s = fmaf(Sm[k], c[k], s);
+        Fz[(size_t)m * plane] = s;
+    }
+}
+
+// Frames of f: F = S f, planar.
+template <int KT>
+__global__ __launch_bounds__(NT) void k_frames(const float *__restrict__ f,
+                                               const float *__restrict__ S,
+                                               float *__restrict__ F, int N, int Nz, int K, int Nt)
+{
+    extern __shared__ float sm[];
+    float *sS = sm;                          // [Nt][KT]
+    float *rows = sm + Nt * KT;              // [NT][KS]
     stage_S<KT>(S, K, Nt, sS);
-    const size_t nvox = (size_t)Nz * N * N;
-    const size_t plane = (size_t)N * N;
+    const size_t plane = (size_t)N * N, nvox = plane * Nz;
+    for (size_t v0 = (size_t)blockIdx.x * NT; v0 < nvox; v0 += (size_t)gridDim.x * NT) {
+        const int nv = (int)std::min<size_t>(NT, nvox - v0);
+        __syncthreads();
+        f_to_lds<KT>(f, v0, nv, K, rows);
+        __syncthreads();
+        if ((int)threadIdx.x < nv)
+            write_frames<KT>(rows + threadIdx.x * kstride(KT), sS, F, v0 + threadIdx.x, plane, Nt);
+    }
+}
+
+// MODE 0: p = grad F (store).  MODE 1: h2 <- shrink(h2 + sigma grad F).
+// MODE 2: no store.  With part != NULL each workgroup writes the FP64 sum of
+// |grad F| over its voxels and frames.
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float lambda2,
+                                             float sigma, float lambda1, float *__restrict__ p,
+                                             double *__restrict__ part, int N, int Nz, int Nt)
+{
+    __shared__ double sh[NT / 64];
+    const size_t plane = (size_t)N * N, nvox = plane * Nz;
     double tvs = 0.0;
     for (size_t v = (size_t)blockIdx.x * NT + threadIdx.x; v < nvox; v += (size_t)gridDim.x * NT) {
         const int q = (int)(v % N);
         const int r = (int)((v / N) % N);
-        const int z = (int)(v / plane);
-        float c0[KT], cx[KT], cy[KT], cz[KT];
-        load_k<KT>(f + v * K, K, c0);
-        const bool hx = q < N - 1, hy = r < N - 1, hz = z < Nz - 1;
-        if (hx) load_k<KT>(f + (v + 1) * K, K, cx);
-        if (hy) load_k<KT>(f + (v + N) * K, K, cy);
-        if (hz) load_k<KT>(f + (v + plane) * K, K, cz);
-        float F0 = frame<KT>(sS, c0);
+        const size_t z = v / plane, pv = v % plane;
+        const bool hx = q < N - 1, hy = r < N - 1, hz = (int)z < Nz - 1;
+        const float *Fz = F + z * Nt * plane + pv;
+        float *pz = (MODE != 2) ? p + z * Nt * 4 * plane + pv : nullptr;
+        float F0 = Fz[0];
         for (int m = 0; m < Nt; ++m) {
-            const float *Sm = sS + m * KT;
-            const float px = hx ? frame<KT>(Sm, cx) - F0 : 0.f;
-            const float py = hy ? frame<KT>(Sm, cy) - F0 : 0.f;
-            const float pz = hz ? frame<KT>(Sm, cz) - F0 : 0.f;
-            float pt = 0.f, F1 = 0.f;
+            const float *Fm = Fz + (size_t)m * plane;
+            const float gx = hx ? Fm[1] - F0 : 0.f;
+            const float gy = hy ? Fm[N] - F0 : 0.f;
+            const float gz = hz ? Fm[(size_t)Nt * plane] - F0 : 0.f;
+            float gt = 0.f, F1 = 0.f;
             if (m < Nt - 1) {
-                F1 = frame<KT>(Sm + KT, c0);
-                pt = lambda2 * (F1 - F0);
+                F1 = Fm[plane];
+                gt = lambda2 * (F1 - F0);
             }
-            if (part) tvs += sqrt((double)px * px + (double)py * py + (double)pz * pz + (double)pt * pt);
-            float4 *dst = (float4 *)(p + (v * Nt + m) * 4);
+            if (part) tvs += sqrt((double)gx * gx + (double)gy * gy + (double)gz * gz + (double)gt * gt);
             if (MODE == 0) {
-                *dst = make_float4(px, py, pz, pt);
+                float *pm = pz + (size_t)m * 4 * plane;
+                pm[0] = gx;
+                pm[plane] = gy;
+                pm[2 * plane] = gz;
+                pm[3 * plane] = gt;
             } else if (MODE == 1) {
-                float4 h = *dst;
-                h.x = fmaf(sigma, px, h.x);
-                h.y = fmaf(sigma, py, h.y);
-                h.z = fmaf(sigma, pz, h.z);
-                h.w = fmaf(sigma, pt, h.w);
-                const float nrm = sqrtf(h.x * h.x + h.y * h.y + h.z * h.z + h.w * h.w);
+                float *pm = pz + (size_t)m * 4 * plane;
+                const float ax = fmaf(sigma, gx, pm[0]);
+                const float ay = fmaf(sigma, gy, pm[plane]);
+                const float az = fmaf(sigma, gz, pm[2 * plane]);
+                const float at = fmaf(sigma, gt, pm[3 * plane]);
+                const float nrm = sqrtf(ax * ax + ay * ay + az * az + at * at);
                 const float sc = lambda1 <= 0.f ? 0.f : (nrm > lambda1 ? lambda1 / nrm : 1.f);
-                *dst = make_float4(h.x * sc, h.y * sc, h.z * sc, h.w * sc);
+                pm[0] = ax * sc;
+                pm[plane] = ay * sc;
+                pm[2 * plane] = az * sc;
+                pm[3 * plane] = at * sc;
             }
             F0 = F1;
         }
@@ -127,60 +172,81 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ f,
 }
 
 // MODE 0: out = S^T div p.  MODE 1 (Fig. 2 steps 5-6):
-//   f+ = f - tau adj + tau S^T div h2;  f~ = 2 f+ - f;  f = f+
-// with FP64 partials |f+ - f|^2 and |f+|^2 per workgroup (2 per block).
+//   f+ = f - tau adj + tau S^T div h2;  f~ = 2 f+ - f;  f = f+;  Ff = S f~
+// with FP64 partials |f+ - f|^2 and |f+|^2 per workgroup when part != NULL.
 template <int KT, int MODE>
 __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                                             const float *__restrict__ S, float lambda2,
                                             float *__restrict__ out, const float *__restrict__ adj,
-                                            float *__restrict__ ft, float tau,
-                                            double *__restrict__ part, int N, int Nz, int K, int Nt)
+                                            float *__restrict__ ft, float *__restrict__ Ff,
+                                            float tau, double *__restrict__ part, int N, int Nz,
+                                            int K, int Nt)
 {
-    extern __shared__ float sS[];
+    constexpr int KS = kstride(KT);
+    extern __shared__ float sm[];
+    float *sS = sm;                          // [Nt][KT]
+    float *rows = sm + Nt * KT;              // [NT][KS]
     __shared__ double sh[NT / 64];
     stage_S<KT>(S, K, Nt, sS);
-    const size_t nvox = (size_t)Nz * N * N;
-    const size_t plane = (size_t)N * N;
+    const size_t plane = (size_t)N * N, nvox = plane * Nz;
     double dn2 = 0.0, fn2 = 0.0;
-    for (size_t v = (size_t)blockIdx.x * NT + threadIdx.x; v < nvox; v += (size_t)gridDim.x * NT) {
-        const int q = (int)(v % N);
-        const int r = (int)((v / N) % N);
-        const int z = (int)(v / plane);
-        float acc[KT];
+    for (size_t v0 = (size_t)blockIdx.x * NT; v0 < nvox; v0 += (size_t)gridDim.x * NT) {
+        const int nv = (int)std::min<size_t>(NT, nvox - v0);
+        const size_t v = v0 + threadIdx.x;
+        __syncthreads();   // S staged; the previous chunk is done with rows
+        if ((int)threadIdx.x < nv) {
+            const int q = (int)(v % N);
+            const int r = (int)((v / N) % N);
+            const size_t z = v / plane, pv = v % plane;
+            const float *pz = pin + z * Nt * 4 * plane + pv;
+            float acc[KT];
 #pragma unroll
-        for (int k = 0; k < KT; ++k) acc[k] = 0.f;
-        const float *pv = pin + v * Nt * 4;
-        const float *px = pin + (q > 0 ? v - 1 : v) * Nt * 4;       // read only when q > 0
-        const float *py = pin + (r > 0 ? v - N : v) * Nt * 4;       // r > 0
-        const float *pz = pin + (z > 0 ? v - plane : v) * Nt * 4;   // z > 0
-        for (int m = 0; m < Nt; ++m) {
-            const float4 c = *(const float4 *)(pv + m * 4);
-            float d = (q < N - 1 ? c.x : 0.f) - (q > 0 ? px[m * 4 + 0] : 0.f);
-            d += (r < N - 1 ? c.y : 0.f) - (r > 0 ? py[m * 4 + 1] : 0.f);
-            d += (z < Nz - 1 ? c.z : 0.f) - (z > 0 ? pz[m * 4 + 2] : 0.f);
-            d += lambda2 * ((m < Nt - 1 ? c.w : 0.f) - (m > 0 ? pv[(m - 1) * 4 + 3] : 0.f));
-            const float *Sm = sS + m * KT;
+            for (int k = 0; k < KT; ++k) acc[k] = 0.f;
+            float tprev = 0.f;
+            for (int m = 0; m < Nt; ++m) {
+                const float *pm = pz + (size_t)m * 4 * plane;
+                float d = (q < N - 1 ? pm[0] : 0.f) - (q > 0 ? pm[-1] : 0.f);
+                d += (r < N - 1 ? pm[plane] : 0.f) - (r > 0 ? pm[plane - N] : 0.f);
+                if (Nz > 1)
+                    d += ((int)z < Nz - 1 ? pm[2 * plane] : 0.f) -
+                         (z > 0 ? *(pm + 2 * plane - (size_t)Nt * 4 * plane) : 0.f);
+                const float tcur = m < Nt - 1 ? pm[3 * plane] : 0.f;
+                d += lambda2 * (tcur - tprev);
+                tprev = tcur;
+                const float *Sm = sS + m * KT;
 #pragma unroll
-            for (int k = 0; k < KT; ++k) acc[k] = fmaf(Sm[k], d, acc[k]);
-        }
-        if (MODE == 0) {
-            store_k<KT>(out + v * K, K, acc);
-        } else {
-            float fo[KT], ad[KT], fnw[KT], fext[KT];
-            load_k<KT>(out + v * K, K, fo);
-            load_k<KT>(adj + v * K, K, ad);
-#pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                fnw[k] = fo[k] - tau * ad[k] + tau * acc[k];
-                const float dd = fnw[k] - fo[k];
-                fext[k] = 2.f * fnw[k] - fo[k];
-                if (k < K) {
-                    dn2 += (double)dd * dd;
-                    fn2 += (double)fnw[k] * fnw[k];
-                }
+                for (int k = 0; k < KT; ++k) acc[k] = fmaf(Sm[k], d, acc[k]);
             }
-            store_k<KT>(out + v * K, K, fnw);
-            store_k<KT>(ft + v * K, K, fext);
+            float *row = rows + threadIdx.x * KS;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) row[k] = acc[k];
+        }
+        __syncthreads();
+        if (MODE == 0) {
+            lds_to_f<KT>(rows, v0, nv, K, out);
+        } else {
+            // element e of the chunk: voxel e / K, channel e % K, contiguous in f
+            float *fb = out + v0 * K;
+            const float *ab = adj + v0 * K;
+            float *tb = ft + v0 * K;
+            const int n = nv * K;
+            for (int e = threadIdx.x; e < n; e += NT) {
+                float *slot = rows + (e / K) * KS + e % K;
+                const float fo = fb[e];
+                const float fnw = fo - tau * ab[e] + tau * slot[0];
+                const float fx = 2.f * fnw - fo;
+                const float dd = fnw - fo;
+                if (part) {
+                    dn2 += (double)dd * dd;
+                    fn2 += (double)fnw * fnw;
+                }
+                fb[e] = fnw;
+                tb[e] = fx;
+                slot[0] = fx;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < nv)
+                write_frames<KT>(rows + threadIdx.x * KS, sS, Ff, v, plane, Nt);
         }
     }
     if (MODE == 1 && part) {
@@ -193,14 +259,26 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
     }
 }
 
-__global__ __launch_bounds__(NT) void k_shrink(float *__restrict__ p, float lambda1, size_t n4)
+__global__ __launch_bounds__(NT) void k_shrink(float *__restrict__ p, float lambda1, size_t plane,
+                                               size_t nzt)
 {
-    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < n4; e += (size_t)gridDim.x * NT) {
-        float4 h = *(float4 *)(p + e * 4);
-        const float nrm = sqrtf(h.x * h.x + h.y * h.y + h.z * h.z + h.w * h.w);
+    // p is [nzt = Nz*Nt][4][plane]
+    const size_t n = nzt * plane;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < n; e += (size_t)gridDim.x * NT) {
+        float *b = p + (e / plane) * 4 * plane + e % plane;
+        const float x = b[0], y = b[plane], z = b[2 * plane], w = b[3 * plane];
+        const float nrm = sqrtf(x * x + y * y + z * z + w * w);
         const float sc = lambda1 <= 0.f ? 0.f : (nrm > lambda1 ? lambda1 / nrm : 1.f);
-        *(float4 *)(p + e * 4) = make_float4(h.x * sc, h.y * sc, h.z * sc, h.w * sc);
+        b[0] = x * sc;
+        b[plane] = y * sc;
+        b[2 * plane] = z * sc;
+        b[3 * plane] = w * sc;
     }
+}
+
+size_t tv_lds(const Plan &p)
+{
+    return ((size_t)p.g.Nt * p.tv.KT + (size_t)NT * kstride(p.tv.KT)) * sizeof(float);
 }
 
 }  // namespace
@@ -211,70 +289,106 @@ unsigned voxel_blocks(const rt_geom &g)
     return (unsigned)std::max<size_t>(1, std::min<size_t>((nvox + NT - 1) / NT, 8192));
 }
 
-#define RT_TV_DISPATCH(NAME, KERNEL, MODE, ...)                                                   \
-    do {                                                                                          \
-        const unsigned nb_ = voxel_blocks(p.g);                                                   \
-        KTimer kt_(NAME, s);                                                                      \
-        const size_t sm_ = (size_t)p.g.Nt * p.tv.KT * sizeof(float);                              \
-        switch (p.tv.KT) {                                                                        \
-        case 8: hipLaunchKernelGGL((KERNEL<8, MODE>), dim3(nb_), dim3(NT), sm_, s, __VA_ARGS__); break;   \
-        case 16: hipLaunchKernelGGL((KERNEL<16, MODE>), dim3(nb_), dim3(NT), sm_, s, __VA_ARGS__); break; \
-        case 32: hipLaunchKernelGGL((KERNEL<32, MODE>), dim3(nb_), dim3(NT), sm_, s, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL((KERNEL<64, MODE>), dim3(nb_), dim3(NT), sm_, s, __VA_ARGS__); break; \
-        }                                                                                         \
-        kt_.stop();                                                                               \
-        RT_HIP(hipGetLastError());                                                                \
-    } while (0)
-
-int launch_tv_grad(const Plan &p, const float *f, float lambda2, float *pout, hipStream_t s)
+int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s)
 {
     if (p.g.Nz == 0) return RT_OK;
-    RT_TV_DISPATCH("k_tv_grad", k_grad, 0, f, p.d_S, lambda2, 0.f, 0.f, pout, (double *)nullptr, p.g.N,
-                   p.g.Nz, p.g.K, p.g.Nt);
+    const unsigned nb = voxel_blocks(p.g);
+    const size_t lds = tv_lds(p);
+    const rt_geom &g = p.g;
+    KTimer kt("k_frames", s);
+    switch (p.tv.KT) {
+    case 8: hipLaunchKernelGGL(k_frames<8>, dim3(nb), dim3(NT), lds, s, f, p.d_S, F, g.N, g.Nz, g.K, g.Nt); break;
+    case 16: hipLaunchKernelGGL(k_frames<16>, dim3(nb), dim3(NT), lds, s, f, p.d_S, F, g.N, g.Nz, g.K, g.Nt); break;
+    case 32: hipLaunchKernelGGL(k_frames<32>, dim3(nb), dim3(NT), lds, s, f, p.d_S, F, g.N, g.Nz, g.K, g.Nt); break;
+    default: hipLaunchKernelGGL(k_frames<64>, dim3(nb), dim3(NT), lds, s, f, p.d_S, F, g.N, g.Nz, g.K, g.Nt); break;
+    }
+    kt.stop();
+    RT_HIP(hipGetLastError());
     return RT_OK;
 }
 
-int launch_grad_shrink(const Plan &p, const float *ft, float *h2, float sigma, float lambda1,
-                       float lambda2, double *part, hipStream_t s)
+static int launch_grad_mode(const Plan &p, int mode, const char *name, const float *F, float *pout,
+                            float sigma, float lambda1, float lambda2, double *part, hipStream_t s)
 {
     if (p.g.Nz == 0) return RT_OK;
-    RT_TV_DISPATCH("k_grad_shrink", k_grad, 1, ft, p.d_S, lambda2, sigma, lambda1, h2, part, p.g.N, p.g.Nz,
-                   p.g.K, p.g.Nt);
+    const unsigned nb = voxel_blocks(p.g);
+    const rt_geom &g = p.g;
+    KTimer kt(name, s);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_grad<0>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_grad<1>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+    else
+        hipLaunchKernelGGL(k_grad<2>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+    kt.stop();
+    RT_HIP(hipGetLastError());
     return RT_OK;
+}
+
+int launch_tv_grad(const Plan &p, const float *f, float lambda2, float *pout, hipStream_t s)
+{
+    int rc = launch_frames(p, f, p.d_frames, s);
+    if (rc) return rc;
+    return launch_grad_mode(p, 0, "k_tv_grad", p.d_frames, pout, 0.f, 0.f, lambda2, nullptr, s);
+}
+
+int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
+                       float lambda2, double *part, hipStream_t s)
+{
+    return launch_grad_mode(p, 1, "k_grad_shrink", Ff, h2, sigma, lambda1, lambda2, part, s);
 }
 
 int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s)
 {
-    if (p.g.Nz == 0) return RT_OK;
-    RT_TV_DISPATCH("k_tv_norm", k_grad, 2, f, p.d_S, lambda2, 0.f, 0.f, (float *)nullptr, part, p.g.N,
-                   p.g.Nz, p.g.K, p.g.Nt);
-    return RT_OK;
+    int rc = launch_frames(p, f, p.d_frames, s);
+    if (rc) return rc;
+    return launch_grad_mode(p, 2, "k_tv_norm", p.d_frames, nullptr, 0.f, 0.f, lambda2, part, s);
+}
+
+template <int MODE>
+static void launch_div_t(const Plan &p, const float *pin, float lambda2, float *out,
+                         const float *adj, float *ft, float *Ff, float tau, double *part,
+                         hipStream_t s)
+{
+    const unsigned nb = voxel_blocks(p.g);
+    const size_t lds = tv_lds(p);
+    const rt_geom &g = p.g;
+    switch (p.tv.KT) {
+    case 8: hipLaunchKernelGGL((k_div<8, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
+    case 16: hipLaunchKernelGGL((k_div<16, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
+    case 32: hipLaunchKernelGGL((k_div<32, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
+    default: hipLaunchKernelGGL((k_div<64, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
+    }
 }
 
 int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hipStream_t s)
 {
     if (p.g.Nz == 0) return RT_OK;
-    RT_TV_DISPATCH("k_tv_div", k_div, 0, pin, p.d_S, lambda2, out, (const float *)nullptr, (float *)nullptr,
-                   0.f, (double *)nullptr, p.g.N, p.g.Nz, p.g.K, p.g.Nt);
+    KTimer kt("k_tv_div", s);
+    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, s);
+    kt.stop();
+    RT_HIP(hipGetLastError());
     return RT_OK;
 }
 
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
-                      float tau, float lambda2, double *part, hipStream_t s)
+                      float *Ff, float tau, float lambda2, double *part, hipStream_t s)
 {
     if (p.g.Nz == 0) return RT_OK;
-    RT_TV_DISPATCH("k_div_update", k_div, 1, h2, p.d_S, lambda2, f, adj, ft, tau, part, p.g.N, p.g.Nz, p.g.K,
-                   p.g.Nt);
+    KTimer kt("k_div_update", s);
+    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, s);
+    kt.stop();
+    RT_HIP(hipGetLastError());
     return RT_OK;
 }
 
 int launch_shrink(const Plan &p, float *pio, float lambda1, size_t n4, hipStream_t s)
 {
-    (void)p;
     if (n4 == 0) return RT_OK;
+    const size_t plane = (size_t)p.g.N * p.g.N;
     const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((n4 + NT - 1) / NT, 8192));
     KTimer kt("k_shrink", s);
-    hipLaunchKernelGGL(k_shrink, dim3(nb), dim3(NT), 0, s, pio, lambda1, n4);
+    hipLaunchKernelGGL(k_shrink, dim3(nb), dim3(NT), 0, s, pio, lambda1, plane, n4 / plane);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;

@@ -142,7 +142,7 @@ class Geom:
 
     @property
     def p_shape(self):
-        return (self.Nz, self.N, self.N, self.Nt, 4)
+        return (self.Nz, self.Nt, 4, self.N, self.N)
 
     def c(self) -> rt_geom:
         return rt_geom(self.N, self.Nz, self.Ns, self.Ntheta, self.Npi, self.K, self.Nt)

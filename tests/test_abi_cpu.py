@@ -72,8 +72,8 @@ def test_job_bytes_accounts_for_state():
     nf = 128 * 512 * 512 * 16
     ng = 1800 * 128 * 512
     n4 = 128 * 512 * 512 * 10
-    state = (2 * nf + 2 * ng + 4 * n4) * 4
-    scratch = 180 * 128 * 512 * 16 * 4
+    state = (2 * nf + 2 * ng + 5 * n4) * 4
+    scratch = 180 * 128 * 512 * 16 * 4 + n4 * 4
     assert state + scratch <= b <= state + scratch + 64 * 2 ** 20
 
 

@@ -100,13 +100,14 @@ def test_tv_parity(G):
     p = rt4d.Plan(G)
     lam1, lam2 = 0.3, 2.5
     f = inputs.uniform(G.f_shape, 5)
-    q = inputs.uniform(G.p_shape, 6)
+    q = inputs.uniform(G.p_shape, 6)                  # library layout (Nz, Nt, 4, N, N)
+    qo = np.ascontiguousarray(q.transpose(0, 3, 4, 1, 2))   # oracle layout (Nz, N, N, Nt, 4)
     pg = p.tv_grad(T(f), lam2).cpu().numpy()
-    assert rel(pg, O.tv_grad(og(G), f, lam2)) <= 1e-6
+    assert rel(pg, O.tv_grad(og(G), f, lam2).transpose(0, 3, 4, 1, 2)) <= 1e-6
     dv = p.tv_div(T(q), lam2).cpu().numpy()
-    assert rel(dv, O.tv_div(og(G), q, lam2)) <= 1e-6
+    assert rel(dv, O.tv_div(og(G), qo, lam2)) <= 1e-6
     sh = p.shrink(T(q), lam1).cpu().numpy()
-    assert rel(sh, O.shrink(q, lam1)) <= 1e-6
+    assert rel(sh, O.shrink(qo, lam1).transpose(0, 3, 4, 1, 2)) <= 1e-6
     assert np.abs(p.shrink(T(q), 0.0).cpu().numpy()).max() == 0.0
 
 
@@ -117,9 +118,10 @@ def test_solve_parity_c1():
                              speed_per_halfturn=1.0)
     g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=1).numpy()
     p = rt4d.Plan(G)
-    L = O.power(og(G), n_pow=20, seed=9)
+    _, r0 = O.solve(og(G), g, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=9)
+    L = r0["L_R"]
     lam1 = 2.0 ** -9 * L * L
-    kw = dict(lambda1=lam1, lambda2=4.0, n_iter=50, tau=0.9 / L, sigma=0.9 / L)
+    kw = dict(lambda1=lam1, lambda2=4.0, n_iter=50, tau=r0["tau"], sigma=r0["sigma"])
     f = torch.zeros(G.f_shape, device=DEV)
     rep = p.solve(T(g), f, **kw)
     fo, ro = O.solve(og(G), g, route="folded", **kw)
@@ -142,11 +144,18 @@ def test_step_rule_power_iteration():
     assert abs(rep["tau"] - ro["tau"]) <= 1e-5 * ro["tau"]
 
 
+def safe_steps(G, g, lambda2):
+    """tau = sigma from the oracle's default rule (tau sigma |K|^2 < 1)."""
+    _, r = O.solve(og(G), g, lambda1=0.0, lambda2=lambda2, n_iter=0, n_pow=30, seed=5)
+    return r["tau"]
+
+
 def test_solve_monitors_and_tolerance():
     G = SHAPES[1]
     p = rt4d.Plan(G)
     g = inputs.uniform(G.g_shape, 8)
-    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=30, tau=0.05, sigma=0.05, check_every=5)
+    st = safe_steps(G, g, 2.0)
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=30, tau=st, sigma=st, check_every=5)
     f = torch.zeros(G.f_shape, device=DEV)
     rep = p.solve(T(g), f, **kw)
     fo, ro = O.solve(og(G), g, **kw)
@@ -205,8 +214,10 @@ def test_empty_and_errors():
 def test_checkpoint_resume_bitwise():
     G = SHAPES[1]
     p = rt4d.Plan(G)
-    g = T(inputs.uniform(G.g_shape, 31))
-    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=50, tau=0.05, sigma=0.05)
+    g0 = inputs.uniform(G.g_shape, 31)
+    g = T(g0)
+    st = safe_steps(G, g0, 2.0)
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=50, tau=st, sigma=st)
     fa = torch.zeros(G.f_shape, device=DEV)
     ja = rt4d.Job(p, g, fa, **kw)
     ja.step(50)
