@@ -55,10 +55,10 @@ def algorithmic(kernel: str, G) -> tuple[str, float]:
         return "alu", 4.0 * G.K * n0 * G.Nz * G.Ns * G.N
     if kernel == "k_backproject":   # 2 taps x 1 FMA per channel per voxel and class
         return "alu", 4.0 * G.K * n0 * G.Nz * G.N * G.N
-    if kernel == "k_grad_shrink":   # read f~, read + write h2
-        return "hbm", nvox * (4.0 * G.K + 2 * 16.0 * G.Nt)
-    if kernel == "k_div_update":    # read h2, f, R*h1; write f, f~
-        return "hbm", nvox * (16.0 * G.Nt + 4 * 4.0 * G.K)
+    if kernel == "k_grad_shrink":   # read the frames of f~, read + write h2
+        return "hbm", nvox * (4.0 * G.Nt + 2 * 16.0 * G.Nt)
+    if kernel == "k_div_update":    # read h2, f, R*h1; write f, f~ and the frames of f~
+        return "hbm", nvox * (16.0 * G.Nt + 4 * 4.0 * G.K + 4.0 * G.Nt)
     if kernel == "k_contract":      # read P, g, h1; write h1
         return "hbm", n0 * G.Nz * G.Ns * 4.0 * G.K + G.Ntheta * G.Nz * G.Ns * 12.0
     if kernel == "k_fold":          # read g, write g~
@@ -133,6 +133,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="uniform random sinogram instead of the phantom (same kernels and "
+                         "launch shapes; fewer auxiliary launches, for counter runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,7 +158,12 @@ def main() -> int:
                              z_axis_range=(G.Nz / 16, G.Nz / 4), rho_range=(0.1, 0.5),
                              speed_per_halfturn=G.N / 64, sphere=(10.0, 60.0, 0.5))
     t0 = time.perf_counter()
-    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=2, device="cuda")
+    if args.kernels_only:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2)
+        g = torch.rand(G.g_shape, generator=gen, device=dev)
+    else:
+        g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=2, device="cuda")
     torch.cuda.synchronize()
     log(f"sinogram synthesised in {time.perf_counter() - t0:.1f} s")
     f = torch.zeros(G.f_shape, device=dev)

@@ -227,7 +227,9 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     const size_t frb = std::max<size_t>(n4_of(p.g), 1) * sizeof(float);
     RT_HIP(hipMalloc(&p.d_frames, frb));
     p.bytes += frb;
-    p.part_cap = (size_t)1 << 18;
+    // FP64 partials: h1 prox, shrink, primal update (two per workgroup), reductions
+    p.part_cap = std::max<size_t>((size_t)1 << 18,
+                                  (size_t)forward_partials(p) + 3 * (size_t)voxel_blocks(p.g) + 64);
     RT_HIP(hipMalloc(&p.d_part, p.part_cap * sizeof(double)));
     RT_HIP(hipMalloc(&p.d_red, 16 * sizeof(double)));
     p.bytes += (p.part_cap + 16) * sizeof(double);

@@ -87,6 +87,20 @@ struct LinePrefetch {
     }
 };
 
+// What the projection does with its sums P(a,z,b,k): store them (EPI_P), or,
+// when one workgroup holds all K channels, contract them with Phi over the
+// Npi half-turns with the s-flip (Sec. 4, eq. radapr and the pi-periodicity)
+// and store g (EPI_G) or apply the h1 prox of Fig. 2 step 3 (EPI_PROX).
+enum { EPI_P = 0, EPI_G = 1, EPI_PROX = 2 };
+struct FwdEpi {
+    const float *phi;     // [Ntheta][K]
+    float *out;           // g (EPI_G) or h1 (EPI_PROX)
+    const float *gdata;   // measured sinogram (EPI_PROX)
+    double *part;         // per-workgroup FP64 sum of (R f~ - g)^2, or NULL
+    float sigma;
+    int mode, n0, Npi;
+};
+
 // Joseph's ray-driven projection of KC channels of slice z for the rays
 // (class, bin) of one group; P(a,z,b,k0..k0+KC) = sum over lines of the
 // linear interpolation between the two positions around the ray, times the
@@ -96,9 +110,10 @@ __global__ __launch_bounds__(FT) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
-    int nbt, int nkc, int stride, unsigned nblocks)
+    int nbt, int nkc, int stride, unsigned nblocks, FwdEpi E)
 {
     extern __shared__ float lines[];   // 2 buffers x [N + 2 slots][stride], slots = positions -1 .. N
+    __shared__ double sh[FT / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
     lid /= nbt;
@@ -190,6 +205,8 @@ __global__ __launch_bounds__(FT) void k_project(
         __syncthreads();
     }
 
+    double d2 = 0.0;
+    const float inv1s = 1.f / (1.f + E.sigma);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int pr = tid + FT * j;
@@ -197,10 +214,34 @@ __global__ __launch_bounds__(FT) void k_project(
         const int b = bt * BT + pr % BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
         if (a < 0 || b >= Ns) continue;
-        float *dst = P + (((size_t)a * Nz + z) * Ns + b) * K + k0;
+        if (E.mode == EPI_P) {
+            float *dst = P + (((size_t)a * Nz + z) * Ns + b) * K + k0;
 #pragma unroll
-        for (int k = 0; k < KC; ++k)
-            if (k0 + k < K) dst[k] = acc[j][k];
+            for (int k = 0; k < KC; ++k)
+                if (k0 + k < K) dst[k] = acc[j][k];
+            continue;
+        }
+        for (int r = 0; r < E.Npi; ++r) {   // every half-turn of class a (K <= KC here)
+            const int i = r * E.n0 + a;
+            const float *ph = E.phi + (size_t)i * K;
+            float v = 0.f;
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+                if (k < K) v = fmaf(ph[k], acc[j][k], v);
+            const int bo = (r & 1) ? Ns - 1 - b : b;
+            const size_t o = ((size_t)i * Nz + z) * Ns + bo;
+            if (E.mode == EPI_G) {
+                E.out[o] = v;
+            } else {
+                const float d = v - E.gdata[o];
+                d2 += (double)d * (double)d;
+                E.out[o] = (E.out[o] + E.sigma * d) * inv1s;
+            }
+        }
+    }
+    if (E.part) {
+        const double sum = block_sum(d2, sh);
+        if (tid == 0) E.part[blockIdx.x] = sum;
     }
 }
 
@@ -251,33 +292,39 @@ __global__ __launch_bounds__(NT) void k_contract(
     }
 }
 
-// g~(a,z,b,k) = sum_rot Phi[rot*n0+a][k] g(rot*n0+a, z, b')  (fold-sum, Sec. 4)
-template <int KT>
+// g~(a,z,b,k) = sum_rot Phi[rot*n0+a][k] g(rot*n0+a, z, b')  (fold-sum, Sec. 4).
+// One thread per (bin, group of 4 channels): consecutive threads write
+// consecutive 16-byte pieces of g~.
 __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
                                              const float *__restrict__ phi,
                                              float *__restrict__ gt, int Nz, int Ns, int K,
                                              int n0, int Npi)
 {
+    const int KQ = (K + 3) / 4;
     const long rows = (long)n0 * Nz;
     for (long row = blockIdx.x; row < rows; row += gridDim.x) {
         const int a = (int)(row / Nz), z = (int)(row % Nz);
-        for (int b = threadIdx.x; b < Ns; b += NT) {
-            float acc[KT];
-#pragma unroll
-            for (int k = 0; k < KT; ++k) acc[k] = 0.f;
+        float *dst = gt + ((size_t)a * Nz + z) * Ns * K;
+        for (int e = threadIdx.x; e < Ns * KQ; e += NT) {
+            const int b = e / KQ, k0 = 4 * (e % KQ);
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
             for (int rot = 0; rot < Npi; ++rot) {
                 const int i = rot * n0 + a;
                 const int bp = (rot & 1) ? Ns - 1 - b : b;
                 const float v = g[((size_t)i * Nz + z) * Ns + bp];
-                const float *ph = phi + (size_t)i * K;
+                const float *ph = phi + (size_t)i * K + k0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    if (k < K) acc[k] = fmaf(ph[k], v, acc[k]);
+                for (int k = 0; k < 4; ++k)
+                    if (k0 + k < K) acc[k] = fmaf(ph[k], v, acc[k]);
             }
-            float *dst = gt + (((size_t)a * Nz + z) * Ns + b) * K;
+            float *d = dst + (size_t)b * K + k0;
+            if ((K & 3) == 0) {
+                *(float4 *)d = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else {
 #pragma unroll
-            for (int k = 0; k < KT; ++k)
-                if (k < K) dst[k] = acc[k];
+                for (int k = 0; k < 4; ++k)
+                    if (k0 + k < K) d[k] = acc[k];
+            }
         }
     }
 }
@@ -400,7 +447,8 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
 }
 
 template <int KC, int PPT, int PF, int VEC>
-static int launch_project_t(const Plan &p, const float *f, hipStream_t s, unsigned nb)
+static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
+                            unsigned nb)
 {
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
@@ -414,26 +462,28 @@ static int launch_project_t(const Plan &p, const float *f, hipStream_t s, unsign
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(FT), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
                        p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
-                       F.nkc, F.stride, nb);
+                       F.nkc, F.stride, nb, E);
     kt.stop();
     return RT_OK;
 }
 
 template <int KC, int PF, int VEC>
-static int launch_project_p(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
+static int launch_project_p(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
+                            unsigned nb, int ppt)
 {
     switch (ppt) {
-    case 1: return launch_project_t<KC, 1, PF, VEC>(p, f, s, nb);
-    case 2: return launch_project_t<KC, 2, PF, VEC>(p, f, s, nb);
-    default: return launch_project_t<KC, 4, PF, VEC>(p, f, s, nb);
+    case 1: return launch_project_t<KC, 1, PF, VEC>(p, f, E, s, nb);
+    case 2: return launch_project_t<KC, 2, PF, VEC>(p, f, E, s, nb);
+    default: return launch_project_t<KC, 4, PF, VEC>(p, f, E, s, nb);
     }
 }
 
 template <int KC, int VEC>
-static int launch_project_k(const Plan &p, const float *f, hipStream_t s, unsigned nb, int ppt)
+static int launch_project_k(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
+                            unsigned nb, int ppt)
 {
-    return p.fwd.pf <= 4 ? launch_project_p<KC, 4, VEC>(p, f, s, nb, ppt)
-                         : launch_project_p<KC, 8, VEC>(p, f, s, nb, ppt);
+    return p.fwd.pf <= 4 ? launch_project_p<KC, 4, VEC>(p, f, E, s, nb, ppt)
+                         : launch_project_p<KC, 8, VEC>(p, f, E, s, nb, ppt);
 }
 
 template <int KC, int VEC>
@@ -452,6 +502,12 @@ static unsigned row_blocks(long rows) { return (unsigned)std::min<long>(rows, 40
 
 }  // namespace
 
+static unsigned project_blocks(const Plan &p)
+{
+    const FwdCfg &F = p.fwd;
+    return (unsigned)p.g.Nz * F.ngroups * F.nkc * F.nbt;
+}
+
 int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
                       float *h1, float sigma, double *part, hipStream_t s)
 {
@@ -460,34 +516,47 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     if (G.Nz == 0) return RT_OK;
     const int pairs = F.A * F.BT;
     const int ppt = pairs <= FT ? 1 : pairs <= 2 * FT ? 2 : 4;
-    const unsigned nb = (unsigned)G.Nz * F.ngroups * F.nkc * F.nbt;
+    const unsigned nb = project_blocks(p);
+    const bool fused = F.nkc == 1;   // all K channels in one workgroup: contract in the epilogue
+    FwdEpi E{};
+    E.phi = p.d_phi;
+    E.out = mode == CONTRACT_STORE ? g : h1;
+    E.gdata = gdata;
+    E.part = fused ? part : nullptr;
+    E.sigma = sigma;
+    E.mode = !fused ? EPI_P : (mode == CONTRACT_STORE ? EPI_G : EPI_PROX);
+    E.n0 = p.n0;
+    E.Npi = G.Npi;
     int rc;
     if (F.vec == 4) {
         switch (F.KC) {
-        case 4: rc = launch_project_k<4, 4>(p, f, s, nb, ppt); break;
-        case 8: rc = launch_project_k<8, 4>(p, f, s, nb, ppt); break;
-        default: rc = launch_project_k<16, 4>(p, f, s, nb, ppt); break;
+        case 4: rc = launch_project_k<4, 4>(p, f, E, s, nb, ppt); break;
+        case 8: rc = launch_project_k<8, 4>(p, f, E, s, nb, ppt); break;
+        default: rc = launch_project_k<16, 4>(p, f, E, s, nb, ppt); break;
         }
     } else {
         switch (F.KC) {
-        case 4: rc = launch_project_k<4, 1>(p, f, s, nb, ppt); break;
-        case 8: rc = launch_project_k<8, 1>(p, f, s, nb, ppt); break;
-        default: rc = launch_project_k<16, 1>(p, f, s, nb, ppt); break;
+        case 4: rc = launch_project_k<4, 1>(p, f, E, s, nb, ppt); break;
+        case 8: rc = launch_project_k<8, 1>(p, f, E, s, nb, ppt); break;
+        default: rc = launch_project_k<16, 1>(p, f, E, s, nb, ppt); break;
         }
     }
     if (rc) return rc;
     RT_HIP(hipGetLastError());
+    if (fused) return RT_OK;
     const unsigned nbc = row_blocks((long)G.Ntheta * G.Nz);
-    float *o = mode == CONTRACT_STORE ? g : h1;
     KTimer kt("k_contract", s);
-    hipLaunchKernelGGL(k_contract, dim3(nbc), dim3(NT), 0, s, p.d_scr, p.d_phi, o, gdata, mode,
-                       sigma, part, G.Nz, G.Ns, G.K, p.n0, G.Ntheta);
+    hipLaunchKernelGGL(k_contract, dim3(nbc), dim3(NT), 0, s, p.d_scr, p.d_phi, E.out, gdata,
+                       mode, sigma, part, G.Nz, G.Ns, G.K, p.n0, G.Ntheta);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
 
-int forward_partials(const Plan &p) { return (int)row_blocks((long)p.g.Ntheta * p.g.Nz); }
+int forward_partials(const Plan &p)
+{
+    return p.fwd.nkc == 1 ? (int)project_blocks(p) : (int)row_blocks((long)p.g.Ntheta * p.g.Nz);
+}
 
 int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s)
 {
@@ -496,12 +565,8 @@ int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s)
     if (G.Nz == 0) return RT_OK;
     const unsigned nbf = row_blocks((long)p.n0 * G.Nz);
     KTimer kt("k_fold", s);
-    switch (p.tv.KT) {
-    case 8: hipLaunchKernelGGL(k_fold<8>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
-    case 16: hipLaunchKernelGGL(k_fold<16>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
-    case 32: hipLaunchKernelGGL(k_fold<32>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
-    default: hipLaunchKernelGGL(k_fold<64>, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K, p.n0, G.Npi); break;
-    }
+    hipLaunchKernelGGL(k_fold, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K,
+                       p.n0, G.Npi);
     kt.stop();
     RT_HIP(hipGetLastError());
     const int ntq = (G.N + 31) / 32, ntr = (G.N + 31) / 32;

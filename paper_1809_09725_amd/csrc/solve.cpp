@@ -13,8 +13,10 @@ using namespace rt;
 
 namespace {
 
-constexpr size_t OFF_GRAD = 4096;            // partial slots in Plan::d_part
-constexpr size_t OFF_DIV = 4096 + 8192;
+// Slots of Plan::d_part: the h1 prox's partials first, then the shrink's,
+// then the (two-wide) primal update's.
+size_t off_grad(const Plan &p) { return (size_t)forward_partials(p); }
+size_t off_div(const Plan &p) { return off_grad(p) + voxel_blocks(p.g); }
 
 // |S|_2 = sqrt(largest eigenvalue of S^T S), cyclic Jacobi on the K x K matrix.
 double s_norm(const Plan &p)
@@ -190,8 +192,8 @@ int step_job(Job &J, int n, hipStream_t s)
     for (int it = 0; it < n && J.iters < P.n_iter && !J.stopped; ++it) {
         const bool check = P.check_every > 0 && (J.iters + 1) % P.check_every == 0;
         double *pf = check ? p.d_part : nullptr;
-        double *pg = check ? p.d_part + OFF_GRAD : nullptr;
-        double *pd = check ? p.d_part + OFF_DIV : nullptr;
+        double *pg = check ? p.d_part + off_grad(p) : nullptr;
+        double *pd = check ? p.d_part + off_div(p) : nullptr;
         // step 3: h1 <- (h1 + sigma (R_T f~ - g)) / (1 + sigma)
         if ((rc = launch_forward_pf(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
         // step 4: h2 <- shrink(h2 + sigma grad S f~)
@@ -228,8 +230,8 @@ int report_job(Job &J, rt_solve_report *rep, hipStream_t s)
         int rc = launch_forward_pf(p, J.f, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
         if (!rc) rc = launch_diff_sq_partials(J.sino, J.g, ng, p.d_part, nbg, s);
         if (!rc) rc = launch_finish(p.d_part, nbg, 1, p.d_red, s);
-        if (!rc) rc = launch_tv_norm(p, J.f, (float)J.prm.lambda2, p.d_part + OFF_GRAD, s);
-        if (!rc) rc = launch_finish(p.d_part + OFF_GRAD, (int)voxel_blocks(p.g), 1, p.d_red + 1, s);
+        if (!rc) rc = launch_tv_norm(p, J.f, (float)J.prm.lambda2, p.d_part + off_grad(p), s);
+        if (!rc) rc = launch_finish(p.d_part + off_grad(p), (int)voxel_blocks(p.g), 1, p.d_red + 1, s);
         if (!rc) rc = fetch(p, 2, m, s);
         if (rc) return rc;
     }

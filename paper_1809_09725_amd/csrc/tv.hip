@@ -76,11 +76,11 @@ __device__ inline void stage_S(const float *__restrict__ S, int K, int Nt, float
 // F[z][m][pv] = sum_k S[m][k] f_k(v) from the LDS row of voxel v.
 template <int KT>
 __device__ inline void write_frames(const float *__restrict__ row, const float *__restrict__ sS,
-                                    float *__restrict__ F, size_t v, size_t plane, int Nt)
+                                    float *__restrict__ F, size_t v, size_t plane, int Nt, int K)
 {
-    float c[KT];
+    float c[KT];   // channels K..KT-1 of the LDS row are padding, never written
 #pragma unroll
-    for (int k = 0; k < KT; ++k) c[k] = row[k];
+    for (int k = 0; k < KT; ++k) c[k] = k < K ? row[k] : 0.f;
     const size_t z = v / plane, pv = v % plane;
     float *Fz = F + z * Nt * plane + pv;
     for (int m = 0; m < Nt; ++m) {
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(NT) void k_frames(const float *__restrict__ f,
         f_to_lds<KT>(f, v0, nv, K, rows);
         __syncthreads();
         if ((int)threadIdx.x < nv)
-            write_frames<KT>(rows + threadIdx.x * kstride(KT), sS, F, v0 + threadIdx.x, plane, Nt);
+            write_frames<KT>(rows + threadIdx.x * kstride(KT), sS, F, v0 + threadIdx.x, plane, Nt, K);
     }
 }
 
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
             }
             __syncthreads();
             if ((int)threadIdx.x < nv)
-                write_frames<KT>(rows + threadIdx.x * KS, sS, Ff, v, plane, Nt);
+                write_frames<KT>(rows + threadIdx.x * KS, sS, Ff, v, plane, Nt, K);
         }
     }
     if (MODE == 1 && part) {
