@@ -453,12 +453,9 @@ static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipS
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
     auto kern = k_project<KC, PPT, PF, VEC>;
-    static bool attr = false;   // raise the dynamic LDS limit once per instantiation
-    if (!attr) {
+    if (F.lds > 64 * 1024)   // beyond the default dynamic LDS limit: ask for what this plan needs
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-        attr = true;
-    }
+                                   (int)F.lds));
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(FT), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
                        p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
