@@ -33,9 +33,10 @@ PEAK_HBM = 8.0e12                               # B/s, MI355X HBM3E
 # FP32 FMA issue without packed math: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9           # 78.6 TFLOP/s
 KERNELS = ("k_project", "k_contract", "k_fold", "k_backproject", "k_grad_shrink",
-           "k_div_update")
+           "k_div_update", "k_project_sf", "k_fold_mfma")
 SOURCES = {"k_project": "proj_pf.hip", "k_contract": "proj_pf.hip", "k_fold": "proj_pf.hip",
-           "k_backproject": "proj_pf.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip"}
+           "k_backproject": "proj_pf.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip",
+           "k_project_sf": "proj_sf.hip", "k_fold_mfma": "proj_sf.hip"}
 
 
 def log(*a):
@@ -53,6 +54,10 @@ def algorithmic(kernel: str, G) -> tuple[str, float]:
     nvox = G.Nz * G.N * G.N
     if kernel == "k_project":       # 2 taps x 1 FMA per channel-sample on every ray step
         return "alu", 4.0 * G.K * n0 * G.Nz * G.Ns * G.N
+    if kernel == "k_project_sf":    # 2 taps x 1 FMA per half-turn on every ray step
+        return "alu", 4.0 * G.Npi * n0 * G.Nz * G.Ns * G.N
+    if kernel == "k_fold_mfma":     # read g, write g~
+        return "hbm", G.Ntheta * G.Nz * G.Ns * 4.0 + n0 * G.Nz * G.Ns * 4.0 * G.K
     if kernel == "k_backproject":   # 2 taps x 1 FMA per channel per voxel and class
         return "alu", 4.0 * G.K * n0 * G.Nz * G.N * G.N
     if kernel == "k_grad_shrink":   # read the frames of f~, read + write h2
@@ -133,6 +138,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--form", choices=("pf", "sf"), default="pf",
+                    help="pf: plain FP32 project-first (the workload's form); sf: precision "
+                         "form (BF16 basis contraction on MFMA, FP32 projection)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="uniform random sinogram instead of the phantom (same kernels and "
                          "launch shapes; fewer auxiliary launches, for counter runs)")
@@ -167,7 +175,9 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"sinogram synthesised in {time.perf_counter() - t0:.1f} s")
     f = torch.zeros(G.f_shape, device=dev)
-    plan = rt4d.Plan(G)
+    form = rt4d.RT_FORM_PF if args.form == "pf" else rt4d.RT_FORM_SF
+    prec = rt4d.RT_PREC_FP32 if args.form == "pf" else rt4d.RT_PREC_BF16MFMA
+    plan = rt4d.Plan(G, form=form, prec=prec)
     # step sizes from the default rule: power iteration for |R_T| (20 steps)
     j0 = rt4d.Job(plan, g, f, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=2)
     rep0 = j0.report()
@@ -226,13 +236,15 @@ def main() -> int:
         "metric": METRIC, "value": round(value, 3), "unit": "Gray-samples/s (1e9 ray-samples/s)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32" if args.form == "pf" else "bf16+f32", "data": "synthetic",
         "config": {"workload": "plain FP32 R_T/R_T* + 4D TV Chambolle-Pock iteration, "
                                "512x512x128 volume, K=16 cosine basis, 1800 projections over "
                                "10 half-turns, 512 bins, 10 TV frames, 40 moving ellipsoids + "
                                "growing sphere, 1% noise",
                    "N": G.N, "Nz": G.Nz, "Ns": G.Ns, "Ntheta": G.Ntheta, "Npi": G.Npi, "K": G.K,
-                   "Nt": G.Nt, "form": "PF", "precision": "fp32", "parallelism": "single GPU"},
+                   "Nt": G.Nt, "form": args.form.upper(),
+                   "precision": "fp32" if args.form == "pf" else "bf16 contraction + fp32 projection",
+                   "parallelism": "single GPU"},
         "iters_per_s": round(1e3 / ms_step, 4),
         "roofline": roof, "kernels": kern,
     }

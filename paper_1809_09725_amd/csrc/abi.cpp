@@ -41,7 +41,7 @@ extern "C" int rt_forward(const rt_plan *plan, const float *f, float *g, void *s
     const Plan &p = plan->impl;
     if ((rc = check_dev_ptr(f, nf_of(p.g), "f"))) return rc;
     if ((rc = check_dev_ptr(g, ng_of(p.g), "g"))) return rc;
-    return launch_forward_pf(p, f, g, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr,
+    return launch_forward(p, f, g, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr,
                              (hipStream_t)stream);
 }
 
@@ -52,7 +52,7 @@ extern "C" int rt_adjoint(const rt_plan *plan, const float *g, float *f_out, voi
     const Plan &p = plan->impl;
     if ((rc = check_dev_ptr(g, ng_of(p.g), "g"))) return rc;
     if ((rc = check_dev_ptr(f_out, nf_of(p.g), "f_out"))) return rc;
-    return launch_adjoint_pf(p, g, f_out, (hipStream_t)stream);
+    return launch_adjoint(p, g, f_out, (hipStream_t)stream);
 }
 
 extern "C" int tv_grad(const rt_plan *plan, const float *f, float lambda2, float *pout, void *stream)

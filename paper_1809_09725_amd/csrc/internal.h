@@ -69,6 +69,13 @@ struct AdjCfg {
     size_t lds = 0;
 };
 
+// Synthesise-first (precision) projector: A classes per group share one
+// 32-column MFMA tile of frames (A * Npi <= 32); lines in chunks of PCH positions.
+struct SfCfg {
+    int A = 1, ngroups = 0, BT = 1, nbt = 1, PCH = 32, cstride = 44, NPM = 4;
+    size_t lds = 0;
+};
+
 struct TvCfg {
     int KT = 8;           // compile-time channel bound (8, 16, 32, 64)
 };
@@ -82,6 +89,7 @@ struct Plan {
     Tables T;
     FwdCfg fwd;
     AdjCfg adj;
+    SfCfg sf;
     TvCfg tv;
 
     float *d_phi = nullptr;     // [Ntheta][K]
@@ -90,6 +98,8 @@ struct Plan {
     double *d_csin = nullptr;
     int *d_gcls = nullptr;      // [ngroups][A], -1 = empty slot
     int *d_gwalk = nullptr;     // [ngroups]
+    int *d_gcls_sf = nullptr;   // class groups of the synthesise-first projector
+    int *d_gwalk_sf = nullptr;
     float *d_scr = nullptr;     // [Ntheta0][Nz][Ns][K]: P (forward), g~ (adjoint)
     float *d_frames = nullptr;  // [Nz][Nt][N][N]: time frames for tv_grad / tv_norm
     double *d_part = nullptr;   // FP64 partial sums
@@ -133,6 +143,16 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
                       float *h1, float sigma, double *part, hipStream_t s);
 int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s);
 int forward_partials(const Plan &p);      // workgroups (= FP64 partials) of the h1 prox
+int launch_backproject(const Plan &p, float *out, hipStream_t s);   // from g~ in d_scr
+// Precision form (proj_sf.hip)
+int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                      float *h1, float sigma, double *part, hipStream_t s);
+int launch_fold_mfma(const Plan &p, const float *g, hipStream_t s);
+unsigned sf_blocks(const Plan &p);
+// Dispatch on the plan's form: R_T (with the h1 prox when mode = CONTRACT_PROX) and R_T*
+int launch_forward(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                   float *h1, float sigma, double *part, hipStream_t s);
+int launch_adjoint(const Plan &p, const float *g, float *out, hipStream_t s);
 unsigned voxel_blocks(const rt_geom &g);  // workgroups (= partials) of the voxel kernels
 
 // 4D TV (tv.hip)

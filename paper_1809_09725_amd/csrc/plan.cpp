@@ -41,9 +41,9 @@ int check_geom(const rt_geom *g)
                     g->Ntheta, g->Npi);
     if (g->Nt > g->Npi)
         return fail(RT_E_SHAPE, "Nt=%d time frames exceed the Npi=%d half-turns", g->Nt, g->Npi);
-    if (g->N > 4096 || g->Ns > 8192 || g->K > 64 || g->Nt > 64)
+    if (g->N > 4096 || g->Ns > 8192 || g->K > 64 || g->Nt > 64 || (int64_t)g->Npi * g->K > 16384)
         return fail(RT_E_SHAPE, "size beyond the supported maximum (N<=4096, Ns<=8192, "
-                    "K<=64, Nt<=64)");
+                    "K<=64, Nt<=64, Npi*K<=16384)");
     return RT_OK;
 }
 
@@ -177,19 +177,49 @@ static int configure(Plan &p)
 
     p.tv.KT = g.K <= 8 ? 8 : g.K <= 16 ? 16 : g.K <= 32 ? 32 : 64;
 
+    // ---- synthesise-first projector: A classes x Npi frames in one 32-column tile
+    std::vector<int> gcls_sf, gwalk_sf;
+    if (p.form == RT_FORM_SF) {
+        SfCfg &C = p.sf;
+        C.A = std::max(1, std::min(4, 32 / g.Npi));
+        C.A = std::min(C.A, (int)std::max(rows.size(), cols.size()));
+        for (int w = 0; w < 2; ++w) {
+            const std::vector<int> &L = w == 0 ? rows : cols;
+            for (size_t i = 0; i < L.size(); i += C.A) {
+                for (int j = 0; j < C.A; ++j) gcls_sf.push_back(i + j < L.size() ? L[i + j] : -1);
+                gwalk_sf.push_back(w);
+            }
+        }
+        C.ngroups = (int)gwalk_sf.size();
+        C.BT = std::min(g.Ns, 512);
+        C.nbt = (g.Ns + C.BT - 1) / C.BT;
+        C.PCH = std::min(512, (g.N + 31) / 32 * 32);
+        C.cstride = C.PCH + 12;   // 16-byte rows whose 4-bank groups differ between columns
+        C.NPM = g.Npi <= 4 ? 4 : g.Npi <= 8 ? 8 : g.Npi <= 12 ? 12 : g.Npi <= 16 ? 16 : 32;
+        C.lds = 2 * 32 * (size_t)C.cstride * sizeof(float);
+    }
+
     // device copies of the group tables
     RT_HIP(hipMalloc(&p.d_gcls, gcls.size() * sizeof(int)));
     RT_HIP(hipMalloc(&p.d_gwalk, gwalk.size() * sizeof(int)));
     RT_HIP(hipMemcpy(p.d_gcls, gcls.data(), gcls.size() * sizeof(int), hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(p.d_gwalk, gwalk.data(), gwalk.size() * sizeof(int), hipMemcpyHostToDevice));
     p.bytes += (gcls.size() + gwalk.size()) * sizeof(int);
+    if (p.form == RT_FORM_SF) {
+        RT_HIP(hipMalloc(&p.d_gcls_sf, gcls_sf.size() * sizeof(int)));
+        RT_HIP(hipMalloc(&p.d_gwalk_sf, gwalk_sf.size() * sizeof(int)));
+        RT_HIP(hipMemcpy(p.d_gcls_sf, gcls_sf.data(), gcls_sf.size() * sizeof(int), hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpy(p.d_gwalk_sf, gwalk_sf.data(), gwalk_sf.size() * sizeof(int), hipMemcpyHostToDevice));
+        p.bytes += (gcls_sf.size() + gwalk_sf.size()) * sizeof(int);
+    }
     return RT_OK;
 }
 
 static void free_plan(Plan &p)
 {
     for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
-                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_scr, (void *)p.d_frames,
+                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_gcls_sf, (void *)p.d_gwalk_sf,
+                      (void *)p.d_scr, (void *)p.d_frames,
                       (void *)p.d_part,
                       (void *)p.d_red})
         if (ptr) (void)hipFree(ptr);
@@ -252,7 +282,10 @@ extern "C" int rt_plan_create(const rt_geom *geom, rt_form form, rt_prec prec, c
         return fail(RT_E_ARG, "unknown precision %d", (int)prec);
     if (prec == RT_PREC_BF16MFMA && form != RT_FORM_SF)
         return fail(RT_E_ARG, "the BF16 contraction needs the synthesise-first form");
-    if (form == RT_FORM_SF) return fail(RT_E_ARG, "synthesise-first form is not available yet");
+    if (form == RT_FORM_SF && prec != RT_PREC_BF16MFMA)
+        return fail(RT_E_ARG, "the synthesise-first form is built with the BF16 contraction only");
+    if (form == RT_FORM_SF && geom->Npi > 32)
+        return fail(RT_E_SHAPE, "the synthesise-first form needs Npi <= 32 (got %d)", geom->Npi);
     if (phi)
         for (size_t e = 0; e < (size_t)geom->Ntheta * geom->K; ++e)
             if (!std::isfinite(phi[e])) return fail(RT_E_ARG, "phi has a non-finite entry");

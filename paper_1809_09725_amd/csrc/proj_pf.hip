@@ -300,10 +300,15 @@ __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
                                              float *__restrict__ gt, int Nz, int Ns, int K,
                                              int n0, int Npi)
 {
+    extern __shared__ float sphi[];   // Phi rows of the current class: [Npi][K]
     const int KQ = (K + 3) / 4;
     const long rows = (long)n0 * Nz;
     for (long row = blockIdx.x; row < rows; row += gridDim.x) {
         const int a = (int)(row / Nz), z = (int)(row % Nz);
+        __syncthreads();
+        for (int e = threadIdx.x; e < Npi * K; e += NT)
+            sphi[e] = phi[(size_t)((e / K) * n0 + a) * K + e % K];
+        __syncthreads();
         float *dst = gt + ((size_t)a * Nz + z) * Ns * K;
         for (int e = threadIdx.x; e < Ns * KQ; e += NT) {
             const int b = e / KQ, k0 = 4 * (e % KQ);
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
                 const int i = rot * n0 + a;
                 const int bp = (rot & 1) ? Ns - 1 - b : b;
                 const float v = g[((size_t)i * Nz + z) * Ns + bp];
-                const float *ph = phi + (size_t)i * K + k0;
+                const float *ph = sphi + rot * K + k0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (k0 + k < K) acc[k] = fmaf(ph[k], v, acc[k]);
@@ -552,20 +557,45 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
 
 int forward_partials(const Plan &p)
 {
+    if (p.form == RT_FORM_SF) return (int)sf_blocks(p);
     return p.fwd.nkc == 1 ? (int)project_blocks(p) : (int)row_blocks((long)p.g.Ntheta * p.g.Nz);
+}
+
+int launch_forward(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                   float *h1, float sigma, double *part, hipStream_t s)
+{
+    if (p.form == RT_FORM_SF) return launch_forward_sf(p, f, g, mode, gdata, h1, sigma, part, s);
+    return launch_forward_pf(p, f, g, mode, gdata, h1, sigma, part, s);
+}
+
+int launch_adjoint(const Plan &p, const float *g, float *out, hipStream_t s)
+{
+    if (p.form == RT_FORM_SF) {
+        int rc = launch_fold_mfma(p, g, s);
+        return rc ? rc : launch_backproject(p, out, s);
+    }
+    return launch_adjoint_pf(p, g, out, s);
 }
 
 int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s)
 {
     const rt_geom &G = p.g;
-    const AdjCfg &B = p.adj;
     if (G.Nz == 0) return RT_OK;
     const unsigned nbf = row_blocks((long)p.n0 * G.Nz);
     KTimer kt("k_fold", s);
-    hipLaunchKernelGGL(k_fold, dim3(nbf), dim3(NT), 0, s, g, p.d_phi, p.d_scr, G.Nz, G.Ns, G.K,
+    hipLaunchKernelGGL(k_fold, dim3(nbf), dim3(NT), (size_t)G.Npi * G.K * sizeof(float), s, g,
+                       p.d_phi, p.d_scr, G.Nz, G.Ns, G.K,
                        p.n0, G.Npi);
     kt.stop();
     RT_HIP(hipGetLastError());
+    return launch_backproject(p, out, s);
+}
+
+int launch_backproject(const Plan &p, float *out, hipStream_t s)
+{
+    const rt_geom &G = p.g;
+    const AdjCfg &B = p.adj;
+    if (G.Nz == 0) return RT_OK;
     const int ntq = (G.N + 31) / 32, ntr = (G.N + 31) / 32;
     const unsigned nb = (unsigned)G.Nz * B.nkc * ntr * ntq;
     if (B.vec == 4) {

@@ -71,14 +71,14 @@ int power_iteration(Job &J, hipStream_t s)
     int rc = launch_seeded_uniform(x, nf, J.prm.seed, s);
     const int nbf = reduce_blocks(0, nf), nbg = reduce_blocks(0, ng);
     for (int it = 0; !rc && it < J.prm.n_pow; ++it) {
-        if ((rc = launch_forward_pf(p, x, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s))) break;
-        if ((rc = launch_adjoint_pf(p, J.sino, y, s))) break;
+        if ((rc = launch_forward(p, x, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s))) break;
+        if ((rc = launch_adjoint(p, J.sino, y, s))) break;
         if ((rc = launch_dot_partials(y, y, nf, p.d_part, nbf, s))) break;
         if ((rc = launch_finish(p.d_part, nbf, 1, p.d_red, s))) break;
         if ((rc = launch_scale(y, p.d_red, nf, s))) break;
         std::swap(x, y);
     }
-    if (!rc) rc = launch_forward_pf(p, x, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
+    if (!rc) rc = launch_forward(p, x, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
     if (!rc) rc = launch_dot_partials(J.sino, J.sino, ng, p.d_part, nbg, s);
     if (!rc) rc = launch_finish(p.d_part, nbg, 1, p.d_red, s);
     double v = 0.0;
@@ -195,11 +195,11 @@ int step_job(Job &J, int n, hipStream_t s)
         double *pg = check ? p.d_part + off_grad(p) : nullptr;
         double *pd = check ? p.d_part + off_div(p) : nullptr;
         // step 3: h1 <- (h1 + sigma (R_T f~ - g)) / (1 + sigma)
-        if ((rc = launch_forward_pf(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
+        if ((rc = launch_forward(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
         // step 4: h2 <- shrink(h2 + sigma grad S f~)
         if ((rc = launch_grad_shrink(p, J.Ff, J.h2, sigma, l1, l2, pg, s))) return rc;
         // steps 5-6: f+ = f - tau R_T* h1 + tau S^T div h2, f~ = 2 f+ - f
-        if ((rc = launch_adjoint_pf(p, J.h1, J.work, s))) return rc;
+        if ((rc = launch_adjoint(p, J.h1, J.work, s))) return rc;
         if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s))) return rc;
         ++J.iters;
         if (check && p.g.Nz > 0) {
@@ -227,7 +227,7 @@ int report_job(Job &J, rt_solve_report *rep, hipStream_t s)
     double m[2] = {0.0, 0.0};
     if (p.g.Nz > 0) {
         const int nbg = reduce_blocks(0, ng);
-        int rc = launch_forward_pf(p, J.f, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
+        int rc = launch_forward(p, J.f, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
         if (!rc) rc = launch_diff_sq_partials(J.sino, J.g, ng, p.d_part, nbg, s);
         if (!rc) rc = launch_finish(p.d_part, nbg, 1, p.d_red, s);
         if (!rc) rc = launch_tv_norm(p, J.f, (float)J.prm.lambda2, p.d_part + off_grad(p), s);

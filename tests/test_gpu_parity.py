@@ -234,3 +234,57 @@ def test_checkpoint_resume_bitwise():
     assert jc.done and jc.iters == 50
     torch.cuda.synchronize()
     assert torch.equal(fa, fc)
+
+
+# ------------------------------------------------- precision form (BF16 MFMA)
+
+SF_SHAPES = [
+    C1,
+    rt4d.Geom(N=45, Nz=3, Ns=50, Ntheta=3 * 37, Npi=3, K=5, Nt=3),
+    rt4d.Geom(N=70, Nz=2, Ns=70, Ntheta=4 * 25, Npi=4, K=12, Nt=4),
+    rt4d.Geom(N=600, Nz=1, Ns=530, Ntheta=12 * 6, Npi=12, K=16, Nt=12),   # 2 chunks, 2 bin tiles
+    rt4d.Geom(N=48, Nz=2, Ns=48, Ntheta=12 * 20, Npi=12, K=32, Nt=6),
+    rt4d.Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1),
+]
+
+
+@pytest.mark.parametrize("G", SF_SHAPES, ids=lambda G: f"N{G.N}z{G.Nz}s{G.Ns}t{G.Ntheta}k{G.K}")
+def test_precision_form_parity(G):
+    """Synthesise-first forward and MFMA fold-sum adjoint: rel-L2 <= 3e-3
+    against the FP64 oracle (BF16 f_k and sinogram, Phi as BF16 hi + lo)."""
+    p = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    for seed, maker in ((41, "uniform"), (42, "smooth")):
+        f = inputs.uniform(G.f_shape, seed) if maker == "uniform" else \
+            inputs.smooth_coeffs(G.N, G.Nz, G.K, seed)
+        s = inputs.uniform(G.g_shape, seed + 100)
+        e_f = rel(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f))
+        e_a = rel(p.adjoint(T(s)).cpu().numpy(), O.adjoint(og(G), s))
+        print(f"case {G} {maker}: precision forward {e_f:.2e} adjoint {e_a:.2e}")
+        assert e_f <= 3e-3 and e_a <= 3e-3
+
+
+def test_precision_form_solve_c1():
+    G = C1
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 3, seed=1, axis_range=(2, 8), rho_range=(0.5, 1.0),
+                             speed_per_halfturn=1.0)
+    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=1).numpy()
+    _, r0 = O.solve(og(G), g, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=9)
+    lam1 = 2.0 ** -9 * r0["L_R"] ** 2
+    kw = dict(lambda1=lam1, lambda2=4.0, n_iter=50, tau=r0["tau"], sigma=r0["sigma"])
+    p = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, **kw)
+    fo, ro = O.solve(og(G), g, route="folded", **kw)
+    e = rel(f.cpu().numpy(), fo)
+    print(f"precision-form C1 solve rel {e:.2e}; objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
+    assert e <= 1e-2
+    assert abs(rep["objective"] - ro["objective"]) <= 1e-2 * abs(ro["objective"])
+
+
+def test_precision_form_deterministic():
+    G = SF_SHAPES[2]
+    p = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    f = T(inputs.uniform(G.f_shape, 5))
+    s = T(inputs.uniform(G.g_shape, 6))
+    assert torch.equal(p.forward(f), p.forward(f))
+    assert torch.equal(p.adjoint(s), p.adjoint(s))
