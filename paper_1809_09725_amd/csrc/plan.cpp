@@ -196,7 +196,7 @@ static int configure(Plan &p)
         C.PCH = std::min(512, (g.N + 31) / 32 * 32);
         C.cstride = C.PCH + 12;   // 16-byte rows whose 4-bank groups differ between columns
         C.NPM = g.Npi <= 4 ? 4 : g.Npi <= 8 ? 8 : g.Npi <= 12 ? 12 : g.Npi <= 16 ? 16 : 32;
-        C.lds = 2 * 32 * (size_t)C.cstride * sizeof(float);
+        C.lds = 32 * (size_t)C.cstride * sizeof(float);
     }
 
     // device copies of the group tables

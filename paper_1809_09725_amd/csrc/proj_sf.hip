@@ -55,7 +55,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
     int nbt, int PCH, int cstride, unsigned nblocks, SfEpi E)
 {
-    extern __shared__ float fr[];   // 2 buffers x [SF_COLS][cstride]: frame c, slot SF_PAD + pos - c0
+    extern __shared__ float fr[];   // [SF_COLS][cstride]: frame c at slot SF_PAD + pos - c0
     __shared__ double sh[ST / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
@@ -66,7 +66,6 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const int walk = gwalk[grp];
     const int Npi = E.Npi;
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
-    const int bufsz = SF_COLS * cstride;
 
     // ---- rays of this thread
     const int b = bt * BT + tid;
@@ -117,93 +116,118 @@ __global__ __launch_bounds__(ST) void k_project_sf(
         }
     }
 
-    // zero the pad slots of both buffers (never written by the frame stores)
-    for (int e = tid; e < 2 * SF_COLS * 2 * SF_PAD; e += ST) {
-        const int bb = e / (SF_COLS * 2 * SF_PAD), w = e % (SF_COLS * 2 * SF_PAD);
-        const int c = w / (2 * SF_PAD), s = w % (2 * SF_PAD);
-        fr[bb * bufsz + c * cstride + (s < SF_PAD ? s : SF_PAD + PCH + (s - SF_PAD))] = 0.f;
+    // zero the pad slots (never written by the frame stores)
+    for (int e = tid; e < SF_COLS * 2 * SF_PAD; e += ST) {
+        const int c = e / (2 * SF_PAD), s = e % (2 * SF_PAD);
+        fr[c * cstride + (s < SF_PAD ? s : SF_PAD + PCH + (s - SF_PAD))] = 0.f;
     }
 
     const size_t zoff = (size_t)z * N * N * K;
     const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;
     const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;
     const int nch = (N + PCH - 1) / PCH;
-    const int tiles = PCH / 32;          // 32-position MFMA row tiles per chunk
-    int buf = 0;
+    const int nsteps = N * nch;          // (line, chunk) steps
 
-    for (int l = 0; l < N; ++l) {
-        const double lc = (double)l - hN;
-        // ray positions on this line
-        int q0[AS];
-        float w0[AS], w1[AS];
-#pragma unroll
-        for (int j = 0; j < AS; ++j) {
-            const double u = fma(lc, slope[j], base[j]);
-            const double fl = floor(u);
-            const int q = (int)fl;
-            const float frc = (float)(u - fl);
-            const bool in = (unsigned)(q + 1) <= (unsigned)N;
-            q0[j] = in ? q : -2;
-            w1[j] = in ? frc * invc[j] : 0.f;
-            w0[j] = in ? (1.f - frc) * invc[j] : 0.f;
-        }
+    // A operand of one step for the wave's two row tiles (wave, wave + 8):
+    // lane holds position c0 + tile*32 + lane%32, channels kb*8 + 4*(lane/32) + 0..3.
+    float4 raw[2][KB];
+    auto load_step = [&](int st) {
+        const int l = st / nch, c0 = (st % nch) * PCH;
         const float *src = f + zoff + (size_t)l * lstep;
-        for (int ch = 0; ch < nch; ++ch) {
-            const int c0 = ch * PCH;
-            float *F = fr + buf * bufsz;
-            // frames of positions [c0, c0 + PCH) on MFMA: wave w does row tiles w, w+8, ...
-            for (int t = wave; t < tiles; t += ST / 64) {
-                const int pos = c0 + t * 32 + (lane & 31);
-                v16f cacc = {};
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb) {
-                    const int k = kb * 8 + 4 * (lane >> 5);
-                    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (pos < N) {
-                        const float *p = src + (size_t)pos * pstep + k;
-                        if ((K & 3) == 0 && k + 3 < K) {
-                            x = *(const float4 *)p;
-                        } else {
-                            x.x = k < K ? p[0] : 0.f;
-                            x.y = k + 1 < K ? p[1] : 0.f;
-                            x.z = k + 2 < K ? p[2] : 0.f;
-                            x.w = k + 3 < K ? p[3] : 0.f;
-                        }
+        for (int h = 0; h < 2; ++h) {
+            const int t = wave + 8 * h;
+            const int pos = c0 + t * 32 + (lane & 31);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const int k = kb * 8 + 4 * (lane >> 5);
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t * 32 < PCH && pos < N) {
+                    const float *p = src + (size_t)pos * pstep + k;
+                    if ((K & 3) == 0 && k + 3 < K) {
+                        x = *(const float4 *)p;
+                    } else {
+                        x.x = k < K ? p[0] : 0.f;
+                        x.y = k + 1 < K ? p[1] : 0.f;
+                        x.z = k + 2 < K ? p[2] : 0.f;
+                        x.w = k + 3 < K ? p[3] : 0.f;
                     }
-                    v4s av;
-                    av[0] = (short)bf16_rne(x.x);
-                    av[1] = (short)bf16_rne(x.y);
-                    av[2] = (short)bf16_rne(x.z);
-                    av[3] = (short)bf16_rne(x.w);
-                    cacc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bhi[kb], cacc, 0, 0, 0);
-                    cacc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, blo[kb], cacc, 0, 0, 0);
                 }
-                // D[row][col]: lane holds column lane%32, rows 8*(v/4) + 4*(lane/32) + v%4
-                float *Fc = F + (lane & 31) * cstride + SF_PAD + t * 32 + 4 * (lane >> 5);
-#pragma unroll
-                for (int g4 = 0; g4 < 4; ++g4)
-                    *(float4 *)(Fc + 8 * g4) = make_float4(cacc[4 * g4], cacc[4 * g4 + 1],
-                                                           cacc[4 * g4 + 2], cacc[4 * g4 + 3]);
+                raw[h][kb] = x;
             }
-            __syncthreads();
-            // taps of the rays whose positions fall in this chunk
+        }
+    };
+    load_step(0);
+
+    int q0[AS];
+    float w0[AS], w1[AS];
+    for (int st = 0; st < nsteps; ++st) {
+        const int l = st / nch, ch = st % nch, c0 = ch * PCH;
+        if (ch == 0) {   // ray positions on line l
+            const double lc = (double)l - hN;
 #pragma unroll
             for (int j = 0; j < AS; ++j) {
-                const int q = q0[j];
-                const bool t0 = q >= c0 && q < c0 + PCH;
-                const bool t1 = q + 1 >= c0 && q + 1 < c0 + PCH;
-                if (!(t0 || t1)) continue;
-                const float a0 = t0 ? w0[j] : 0.f, a1 = t1 ? w1[j] : 0.f;
-                const float *Fj = F + (j * Npi) * cstride + SF_PAD + (q - c0);   // slot of q
+                const double u = fma(lc, slope[j], base[j]);
+                const double fl = floor(u);
+                const int q = (int)fl;
+                const float frc = (float)(u - fl);
+                const bool in = (unsigned)(q + 1) <= (unsigned)N;
+                q0[j] = in ? q : -2;
+                w1[j] = in ? frc * invc[j] : 0.f;
+                w0[j] = in ? (1.f - frc) * invc[j] : 0.f;
+            }
+        }
+        // this step's A operands to BF16, then start the next step's loads
+        v4s av[2][KB];
 #pragma unroll
-                for (int r = 0; r < NPM; ++r) {
-                    if (r < Npi) {
-                        const float x0 = Fj[r * cstride], x1 = Fj[r * cstride + 1];
-                        acc[j][r] = fmaf(a1, x1, fmaf(a0, x0, acc[j][r]));
-                    }
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                av[h][kb][0] = (short)bf16_rne(raw[h][kb].x);
+                av[h][kb][1] = (short)bf16_rne(raw[h][kb].y);
+                av[h][kb][2] = (short)bf16_rne(raw[h][kb].z);
+                av[h][kb][3] = (short)bf16_rne(raw[h][kb].w);
+            }
+        if (st + 1 < nsteps) load_step(st + 1);
+        // frames of the two tiles on MFMA (two independent accumulators)
+        v16f c0acc = {}, c1acc = {};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            c0acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[0][kb], bhi[kb], c0acc, 0, 0, 0);
+            c1acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[1][kb], bhi[kb], c1acc, 0, 0, 0);
+            c0acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[0][kb], blo[kb], c0acc, 0, 0, 0);
+            c1acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[1][kb], blo[kb], c1acc, 0, 0, 0);
+        }
+        __syncthreads();   // the previous step's taps are done with the frame buffer
+        // D[row][col]: lane holds column lane%32, rows 8*(v/4) + 4*(lane/32) + v%4
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = wave + 8 * h;
+            if (t * 32 >= PCH) continue;
+            const v16f &cc = h ? c1acc : c0acc;
+            float *Fc = fr + (lane & 31) * cstride + SF_PAD + t * 32 + 4 * (lane >> 5);
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4)
+                *(float4 *)(Fc + 8 * g4) =
+                    make_float4(cc[4 * g4], cc[4 * g4 + 1], cc[4 * g4 + 2], cc[4 * g4 + 3]);
+        }
+        __syncthreads();
+        // taps of the rays whose positions fall in this chunk
+#pragma unroll
+        for (int j = 0; j < AS; ++j) {
+            const int q = q0[j];
+            const bool t0 = q >= c0 && q < c0 + PCH;
+            const bool t1 = q + 1 >= c0 && q + 1 < c0 + PCH;
+            if (!(t0 || t1)) continue;
+            const float a0 = t0 ? w0[j] : 0.f, a1 = t1 ? w1[j] : 0.f;
+            const float *Fj = fr + (j * Npi) * cstride + SF_PAD + (q - c0);   // slot of q
+#pragma unroll
+            for (int r = 0; r < NPM; ++r) {
+                if (r < Npi) {
+                    const float x0 = Fj[r * cstride], x1 = Fj[r * cstride + 1];
+                    acc[j][r] = fmaf(a1, x1, fmaf(a0, x0, acc[j][r]));
                 }
             }
-            buf ^= 1;
         }
     }
 
