@@ -48,8 +48,8 @@ def c2_geom():
     return rt4d.Geom(N=512, Nz=128, Ns=512, Ntheta=1800, Npi=10, K=16, Nt=10)
 
 
-def algorithmic(kernel: str, G) -> tuple[str, float]:
-    """(bound, algorithmic flops or bytes of one launch)."""
+def algorithmic(kernel: str, G, sf: bool = False) -> tuple[str, float]:
+    """(bound, algorithmic flops or bytes of one launch); sf: precision form."""
     n0 = G.Ntheta // G.Npi
     nvox = G.Nz * G.N * G.N
     if kernel == "k_project":       # 2 taps x 1 FMA per channel-sample on every ray step
@@ -63,7 +63,8 @@ def algorithmic(kernel: str, G) -> tuple[str, float]:
     if kernel == "k_grad_shrink":   # read the frames of f~, read + write h2
         return "hbm", nvox * (4.0 * G.Nt + 2 * 16.0 * G.Nt)
     if kernel == "k_div_update":    # read h2, f, R*h1; write f, f~ and the frames of f~
-        return "hbm", nvox * (16.0 * G.Nt + 4 * 4.0 * G.K + 4.0 * G.Nt)
+        shadow = 2.0 * ((G.K + 15) // 16 * 16) if sf else 0.0   # + the BF16 shadow of f~
+        return "hbm", nvox * (16.0 * G.Nt + 4 * 4.0 * G.K + 4.0 * G.Nt + shadow)
     if kernel == "k_contract":      # read P, g, h1; write h1
         return "hbm", n0 * G.Nz * G.Ns * 4.0 * G.K + G.Ntheta * G.Nz * G.Ns * 12.0
     if kernel == "k_fold":          # read g, write g~
@@ -90,8 +91,8 @@ def traffic_from_profiles(kernel: str):
     try:
         if kv.get("source_sha") != source_sha(kernel):
             return None
-        scale = float(kv["copy_scale"])
-        return (float(kv["fetch_kib_per_dispatch"]) + float(kv["write_kib_per_dispatch"])) * 1024 * scale
+        return 1024.0 * (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"]) +
+                         float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]))
     except (KeyError, ValueError):
         return None
 
@@ -215,7 +216,7 @@ def main() -> int:
         f"rel_change {rep['rel_change']:.3g}")
 
     dom = max((k for k in per if k in KERNELS), key=lambda k: per[k][0])
-    bound, work = algorithmic(dom, G)
+    bound, work = algorithmic(dom, G, args.form == "sf")
     dur = per[dom][0] / per[dom][1] * 1e-3
     if bound == "hbm":
         achieved, peak, unit = work / dur / 1e9, PEAK_HBM / 1e9, "GB/s"
@@ -228,7 +229,7 @@ def main() -> int:
     for k, (ms, n) in per.items():
         if k not in KERNELS:
             continue
-        b, w = algorithmic(k, G)
+        b, w = algorithmic(k, G, args.form == "sf")
         d = ms / n * 1e-3
         kern[k] = {"ms": round(d * 1e3, 4), "bound": b,
                    "frac": round((w / d) / (PEAK_HBM if b == "hbm" else PEAK_FP32_VALU), 4)}

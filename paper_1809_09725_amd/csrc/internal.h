@@ -69,10 +69,12 @@ struct AdjCfg {
     size_t lds = 0;
 };
 
-// Synthesise-first (precision) projector: A classes per group share one
-// 32-column MFMA tile of frames (A * Npi <= 32); lines in chunks of PCH positions.
+// Synthesise-first (precision) projector: A classes per group, NPP frame
+// columns each (Npi rounded up to 4), A * NPP <= 32 columns in one MFMA tile;
+// lines in chunks of PCH positions, CS floats per LDS row; the BF16 shadow of
+// f has KP = K rounded up to 16 channels per voxel.
 struct SfCfg {
-    int A = 1, ngroups = 0, BT = 1, nbt = 1, PCH = 32, cstride = 44, NPM = 4;
+    int A = 1, ngroups = 0, BT = 1, nbt = 1, PCH = 32, CS = 20, NPP = 4, KP = 16;
     size_t lds = 0;
 };
 
@@ -105,6 +107,10 @@ struct Plan {
     double *d_part = nullptr;   // FP64 partial sums
     size_t part_cap = 0;        // doubles in d_part
     double *d_red = nullptr;    // final FP64 sums (16 doubles)
+    void *d_f16 = nullptr;      // synthesise-first: BF16 shadow of f, [Nz][N][N][KP]
+    // bumped by every write of d_f16, so that a job knows whether the shadow
+    // still holds its own f~
+    mutable unsigned long long shadow_gen = 0;
     size_t bytes = 0;
 };
 
@@ -121,6 +127,7 @@ struct Job {
     float *sino = nullptr;      // R_T f for the report, sinogram shaped
     double tau = 0, sigma = 0, L_R = 0, L_G = 0;
     int iters = 0;
+    unsigned long long shadow_gen = ~0ull;   // plan shadow_gen when d_f16 last held this f~
     bool stopped = false;
     double residual = 0, objective = 0, rel_change = 0;
     size_t bytes = 0;
@@ -132,6 +139,7 @@ inline size_t ng_of(const rt_geom &g) { return (size_t)g.Ntheta * g.Nz * g.Ns; }
 inline size_t n4_of(const rt_geom &g) { return (size_t)g.Nz * g.N * g.N * g.Nt; }
 size_t job_state_bytes(const rt_geom &g);
 size_t plan_scratch_bytes(const rt_geom &g);
+size_t shadow_bytes(const rt_geom &g);   // BF16 shadow of f (synthesise-first plans)
 
 int check_geom(const rt_geom *g);
 int check_plan(const rt_plan *p);
@@ -146,9 +154,13 @@ int forward_partials(const Plan &p);      // workgroups (= FP64 partials) of the
 int launch_backproject(const Plan &p, float *out, hipStream_t s);   // from g~ in d_scr
 // Precision form (proj_sf.hip)
 int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
-                      float *h1, float sigma, double *part, hipStream_t s);
+                      float *h1, float sigma, double *part, hipStream_t s);   // converts f first
+int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, float *h1,
+                        float sigma, double *part, hipStream_t s);            // from d_f16
+int launch_to_bf16(const Plan &p, const float *f, hipStream_t s);            // f -> d_f16
 int launch_fold_mfma(const Plan &p, const float *g, hipStream_t s);
 unsigned sf_blocks(const Plan &p);
+int sf_slots(int npp);   // classes per workgroup the kernel is built for
 // Dispatch on the plan's form: R_T (with the h1 prox when mode = CONTRACT_PROX) and R_T*
 int launch_forward(const Plan &p, const float *f, float *g, int mode, const float *gdata,
                    float *h1, float sigma, double *part, hipStream_t s);
@@ -165,7 +177,8 @@ int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s);
 int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
                        float lambda2, double *part, hipStream_t s);
 // f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; Ff = S f~;
-// partials |f+ - f|^2, |f+|^2
+// partials |f+ - f|^2, |f+|^2; synthesise-first plans also refresh the BF16
+// shadow d_f16 of f~ (and bump shadow_gen)
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
                       float *Ff, float tau, float lambda2, double *part, hipStream_t s);
 // sum over voxels and frames of |grad S f| (FP64 partials)

@@ -59,6 +59,11 @@ size_t plan_scratch_bytes(const rt_geom &g)
     return n0 * g.Nz * g.Ns * g.K * sizeof(float);
 }
 
+size_t shadow_bytes(const rt_geom &g)
+{
+    return (size_t)g.Nz * g.N * g.N * ((g.K + 15) / 16 * 16) * 2;
+}
+
 size_t job_state_bytes(const rt_geom &g)
 {
     return (2 * nf_of(g) + 2 * ng_of(g) + 5 * n4_of(g)) * sizeof(float);
@@ -177,12 +182,12 @@ static int configure(Plan &p)
 
     p.tv.KT = g.K <= 8 ? 8 : g.K <= 16 ? 16 : g.K <= 32 ? 32 : 64;
 
-    // ---- synthesise-first projector: A classes x Npi frames in one 32-column tile
+    // ---- synthesise-first projector: A classes x NPP frame columns in one 32-column tile
     std::vector<int> gcls_sf, gwalk_sf;
     if (p.form == RT_FORM_SF) {
         SfCfg &C = p.sf;
-        C.A = std::max(1, std::min(4, 32 / g.Npi));
-        C.A = std::min(C.A, (int)std::max(rows.size(), cols.size()));
+        C.NPP = (g.Npi + 3) / 4 * 4;
+        C.A = std::min(sf_slots(C.NPP), (int)std::max(rows.size(), cols.size()));
         for (int w = 0; w < 2; ++w) {
             const std::vector<int> &L = w == 0 ? rows : cols;
             for (size_t i = 0; i < L.size(); i += C.A) {
@@ -194,9 +199,12 @@ static int configure(Plan &p)
         C.BT = std::min(g.Ns, 512);
         C.nbt = (g.Ns + C.BT - 1) / C.BT;
         C.PCH = std::min(512, (g.N + 31) / 32 * 32);
-        C.cstride = C.PCH + 12;   // 16-byte rows whose 4-bank groups differ between columns
-        C.NPM = g.Npi <= 4 ? 4 : g.Npi <= 8 ? 8 : g.Npi <= 12 ? 12 : g.Npi <= 16 ? 16 : 32;
-        C.lds = 32 * (size_t)C.cstride * sizeof(float);
+        C.KP = (g.K + 15) / 16 * 16;
+        // an odd number of 16-byte groups per row: 16 consecutive positions
+        // of a b128 access fall in distinct bank groups
+        const int c4 = C.A * C.NPP / 4;
+        C.CS = 4 * (c4 % 2 ? c4 : c4 + 1);
+        C.lds = (size_t)(C.PCH + 2) * C.CS * sizeof(float);
     }
 
     // device copies of the group tables
@@ -219,7 +227,7 @@ static void free_plan(Plan &p)
 {
     for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
                       (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_gcls_sf, (void *)p.d_gwalk_sf,
-                      (void *)p.d_scr, (void *)p.d_frames,
+                      (void *)p.d_scr, (void *)p.d_frames, p.d_f16,
                       (void *)p.d_part,
                       (void *)p.d_red})
         if (ptr) (void)hipFree(ptr);
@@ -257,6 +265,11 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     const size_t frb = std::max<size_t>(n4_of(p.g), 1) * sizeof(float);
     RT_HIP(hipMalloc(&p.d_frames, frb));
     p.bytes += frb;
+    if (form == RT_FORM_SF) {
+        const size_t sb = std::max<size_t>(shadow_bytes(p.g), 256);
+        RT_HIP(hipMalloc(&p.d_f16, sb));
+        p.bytes += sb;
+    }
     // FP64 partials: h1 prox, shrink, primal update (two per workgroup), reductions
     p.part_cap = std::max<size_t>((size_t)1 << 18,
                                   (size_t)forward_partials(p) + 3 * (size_t)voxel_blocks(p.g) + 64);

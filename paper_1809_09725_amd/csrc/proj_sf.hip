@@ -2,15 +2,16 @@
 // (and its transpose) in BF16 on the matrix cores with FP32 accumulation,
 // the projection itself in FP32.
 //
-// Forward, synthesise-first: for each staged line (row or column) of slice z
-// the states of the line at the Npi half-turns of the workgroup's angle
-// classes are formed on MFMA,
-//   F[c][pos] = sum_k f_k(line, pos) Phi[i(c)][k],   c = (class slot, half-turn),
-// with f_k rounded to BF16 and Phi split into BF16 hi + lo, FP32 accumulate;
-// each ray (class, bin) then takes Joseph's two interpolation taps on the
-// Npi frame lines of its class (Sec. 2 eq. Rfwd: the state at time t_i is
-// projected at theta_i; the pi-periodicity of Sec. 4 lets every half-turn of
-// a class share one ray walk, odd half-turns landing on bin Ns-1-b).
+// Forward, synthesise-first: for each line (row or column) of slice z the
+// states of the line at the Npi half-turns of the workgroup's angle classes
+// are formed on MFMA,
+//   F[c][pos] = sum_k Phi[i(c)][k] f_k(line, pos),   c = (class slot, half-turn),
+// from a BF16 shadow of f (kept beside f~ by the primal update, or converted
+// on entry) and Phi split into BF16 hi + lo parts, FP32 accumulate; each ray
+// (class, bin) then takes Joseph's two interpolation taps on the frames of
+// its class (Sec. 2 eq. Rfwd: the state at time t_i is projected at
+// theta_i; the pi-periodicity of Sec. 4 lets every half-turn of a class share
+// one ray walk, odd half-turns landing on bin Ns-1-b).
 //
 // Adjoint: the fold-sum g~(a,z,b,k) = sum_r Phi[r*Ntheta0+a][k] g(r*Ntheta0+a,
 // z, b') (Sec. 4) as BF16 MFMA products with FP32 accumulation, then the FP32
@@ -24,10 +25,9 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int ST = 512;        // threads of a synthesise-first workgroup (8 wave64)
-constexpr int SF_COLS = 32;    // frame columns per workgroup: one 32-wide MFMA tile
-constexpr int SF_PAD = 4;      // LDS slots before position 0 of a chunk (16-byte alignment)
 
 // FP32 -> BF16 with round-to-nearest-even (finite inputs).
 __device__ inline unsigned short bf16_rne(float x)
@@ -45,17 +45,26 @@ struct SfEpi {
     int prox, n0, Npi;
 };
 
-// Workgroup: slice z, a group of A classes of one walk direction, bins
-// [bt*BT, bt*BT + BT).  Thread t owns the rays (slot j, bin bt*BT + t) for
-// the A slots.  NPM: accumulators per ray (>= Npi).  KB: K / 8 (MFMA k-steps).
-template <int NPM, int KB, int AS>
+// Forward, synthesise-first.  Workgroup: slice z, a group of A classes of one
+// walk direction, bins [bt*BT, bt*BT + BT).  Thread t owns the rays (slot j,
+// bin bt*BT + t) for the A slots.  NPP: frame columns per class (Npi rounded
+// up to 4, the padding columns are zero); KB: MFMA k-steps of 16 channels.
+//
+// The frames F[c][pos] = sum_k Phi[i(c)][k] f_k(pos) of a chunk of PCH
+// positions are one v_mfma_f32_32x32x16_bf16 product per 32-position tile:
+// A = Phi rows of the 32 frame columns (hi and lo BF16 parts), B = the BF16
+// shadow of f.  They land in LDS position-major, row 1 + pos - c0 holding the
+// A*NPP frames of position pos, so that a ray's tap at one position is NPP/4
+// 16-byte reads, the access of the plain form's staged lines.
+template <int NPP, int KB, int AS>
 __global__ __launch_bounds__(ST) void k_project_sf(
-    const float *__restrict__ f, const float *__restrict__ phi, const int *__restrict__ gcls,
+    const __bf16 *__restrict__ f16, const float *__restrict__ phi, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
-    int nbt, int PCH, int cstride, unsigned nblocks, SfEpi E)
+    int nbt, int PCH, int CS, unsigned nblocks, SfEpi E)
 {
-    extern __shared__ float fr[];   // [SF_COLS][cstride]: frame c at slot SF_PAD + pos - c0
+    constexpr int KP = 16 * KB;
+    extern __shared__ float fr[];   // [PCH + 2][CS]; rows 0 and PCH + 1 stay zero
     __shared__ double sh[ST / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
@@ -65,6 +74,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int walk = gwalk[grp];
     const int Npi = E.Npi;
+    const int CW = A * NPP;        // frame columns in use
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
 
     // ---- rays of this thread
@@ -74,7 +84,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
 #pragma unroll
     for (int j = 0; j < AS; ++j) {
         const int a = j < A ? gcls[grp * A + j] : -1;
-        base[j] = -1.0e9;   // far outside: both taps get weight 0
+        base[j] = -1.0e9;   // far outside: never tapped
         slope[j] = 0.0;
         invc[j] = 0.f;
         if (a >= 0 && tid < BT && b < Ns) {
@@ -90,71 +100,52 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             }
         }
     }
-    float acc[AS][NPM];
+    float acc[AS][NPP];
 #pragma unroll
     for (int j = 0; j < AS; ++j)
 #pragma unroll
-        for (int r = 0; r < NPM; ++r) acc[j][r] = 0.f;
+        for (int r = 0; r < NPP; ++r) acc[j][r] = 0.f;
 
-    // ---- MFMA B operand: Phi^T[k][c] for the 32 frame columns, hi and lo parts.
-    // lane holds column c = lane % 32, channels kb*8 + 4*(lane/32) + 0..3.
-    v4s bhi[KB], blo[KB];
+    // ---- MFMA A operand: Phi[i(c)][k] of frame column c = lane % 32 (slot
+    // c / NPP, half-turn c % NPP), channels kb*16 + 8*(lane/32) + 0..7
+    v8bf ahi[KB], alo[KB];
     {
-        const int c = lane & 31, slot = c / Npi, r = c % Npi;
-        const int a = (slot < A) ? gcls[grp * A + slot] : -1;
+        const int c = lane & 31, slot = c / NPP, r = c % NPP;
+        const int a = (slot < A && r < Npi) ? gcls[grp * A + slot] : -1;
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
+        for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = kb * 8 + 4 * (lane >> 5) + q;
-                float v = 0.f;
-                if (a >= 0 && k < K) v = phi[(size_t)(r * E.n0 + a) * K + k];
-                const unsigned short h = bf16_rne(v);
-                bhi[kb][q] = (short)h;
-                blo[kb][q] = (short)bf16_rne(v - bf16_val(h));
+            for (int q = 0; q < 8; ++q) {
+                const int k = kb * 16 + 8 * (lane >> 5) + q;
+                const float v = (a >= 0 && k < K) ? phi[(size_t)(r * E.n0 + a) * K + k] : 0.f;
+                const __bf16 h = (__bf16)v;
+                ahi[kb][q] = h;
+                alo[kb][q] = (__bf16)(v - (float)h);
             }
-        }
     }
 
-    // zero the pad slots (never written by the frame stores)
-    for (int e = tid; e < SF_COLS * 2 * SF_PAD; e += ST) {
-        const int c = e / (2 * SF_PAD), s = e % (2 * SF_PAD);
-        fr[c * cstride + (s < SF_PAD ? s : SF_PAD + PCH + (s - SF_PAD))] = 0.f;
-    }
+    for (int e = tid; e < 2 * CS; e += ST) fr[e < CS ? e : (PCH + 1) * CS + (e - CS)] = 0.f;
 
-    const size_t zoff = (size_t)z * N * N * K;
-    const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;
-    const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;
+    const __bf16 *fz = f16 + (size_t)z * N * N * KP;
+    const size_t lstep = walk == 0 ? (size_t)N * KP : (size_t)KP;
+    const size_t pstep = walk == 0 ? (size_t)KP : (size_t)N * KP;
     const int nch = (N + PCH - 1) / PCH;
     const int nsteps = N * nch;          // (line, chunk) steps
 
-    // A operand of one step for the wave's two row tiles (wave, wave + 8):
-    // lane holds position c0 + tile*32 + lane%32, channels kb*8 + 4*(lane/32) + 0..3.
-    float4 raw[2][KB];
+    // B operand of one step for the wave's position tiles wave and wave + 8:
+    // lane holds position c0 + tile*32 + lane%32, channels kb*16 + 8*(lane/32) + 0..7
+    v8bf raw[2][KB];
     auto load_step = [&](int st) {
         const int l = st / nch, c0 = (st % nch) * PCH;
-        const float *src = f + zoff + (size_t)l * lstep;
+        const __bf16 *src = fz + (size_t)l * lstep + 8 * (lane >> 5);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = wave + 8 * h;
             const int pos = c0 + t * 32 + (lane & 31);
+            const bool in = t * 32 < PCH && pos < N;
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                const int k = kb * 8 + 4 * (lane >> 5);
-                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (t * 32 < PCH && pos < N) {
-                    const float *p = src + (size_t)pos * pstep + k;
-                    if ((K & 3) == 0 && k + 3 < K) {
-                        x = *(const float4 *)p;
-                    } else {
-                        x.x = k < K ? p[0] : 0.f;
-                        x.y = k + 1 < K ? p[1] : 0.f;
-                        x.z = k + 2 < K ? p[2] : 0.f;
-                        x.w = k + 3 < K ? p[3] : 0.f;
-                    }
-                }
-                raw[h][kb] = x;
-            }
+            for (int kb = 0; kb < KB; ++kb)
+                raw[h][kb] = in ? *(const v8bf *)(src + (size_t)pos * pstep + kb * 16) : v8bf{};
         }
     };
     load_step(0);
@@ -162,8 +153,8 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     int q0[AS];
     float w0[AS], w1[AS];
     for (int st = 0; st < nsteps; ++st) {
-        const int l = st / nch, ch = st % nch, c0 = ch * PCH;
-        if (ch == 0) {   // ray positions on line l
+        const int l = st / nch, c0 = (st % nch) * PCH;
+        if (c0 == 0) {   // ray positions on line l
             const double lc = (double)l - hN;
 #pragma unroll
             for (int j = 0; j < AS; ++j) {
@@ -172,61 +163,56 @@ __global__ __launch_bounds__(ST) void k_project_sf(
                 const int q = (int)fl;
                 const float frc = (float)(u - fl);
                 const bool in = (unsigned)(q + 1) <= (unsigned)N;
-                q0[j] = in ? q : -2;
+                q0[j] = in ? q : -(1 << 28);
                 w1[j] = in ? frc * invc[j] : 0.f;
                 w0[j] = in ? (1.f - frc) * invc[j] : 0.f;
             }
         }
-        // this step's A operands to BF16, then start the next step's loads
-        v4s av[2][KB];
+        v8bf bop[2][KB];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                av[h][kb][0] = (short)bf16_rne(raw[h][kb].x);
-                av[h][kb][1] = (short)bf16_rne(raw[h][kb].y);
-                av[h][kb][2] = (short)bf16_rne(raw[h][kb].z);
-                av[h][kb][3] = (short)bf16_rne(raw[h][kb].w);
-            }
+            for (int kb = 0; kb < KB; ++kb) bop[h][kb] = raw[h][kb];
         if (st + 1 < nsteps) load_step(st + 1);
-        // frames of the two tiles on MFMA (two independent accumulators)
-        v16f c0acc = {}, c1acc = {};
+        v16f d0 = {}, d1 = {};
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-            c0acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[0][kb], bhi[kb], c0acc, 0, 0, 0);
-            c1acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[1][kb], bhi[kb], c1acc, 0, 0, 0);
-            c0acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[0][kb], blo[kb], c0acc, 0, 0, 0);
-            c1acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[1][kb], blo[kb], c1acc, 0, 0, 0);
+            d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[kb], bop[0][kb], d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[kb], bop[1][kb], d1, 0, 0, 0);
+            d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[kb], bop[0][kb], d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[kb], bop[1][kb], d1, 0, 0, 0);
         }
-        __syncthreads();   // the previous step's taps are done with the frame buffer
-        // D[row][col]: lane holds column lane%32, rows 8*(v/4) + 4*(lane/32) + v%4
+        __syncthreads();   // the previous step's taps are done with the frames
+        // D[c][pos]: lane holds position lane%32 of its tile, columns 8g + 4(lane/32) + 0..3
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = wave + 8 * h;
             if (t * 32 >= PCH) continue;
-            const v16f &cc = h ? c1acc : c0acc;
-            float *Fc = fr + (lane & 31) * cstride + SF_PAD + t * 32 + 4 * (lane >> 5);
+            const v16f &d = h ? d1 : d0;
+            float *row = fr + (1 + t * 32 + (lane & 31)) * CS + 4 * (lane >> 5);
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4)
-                *(float4 *)(Fc + 8 * g4) =
-                    make_float4(cc[4 * g4], cc[4 * g4 + 1], cc[4 * g4 + 2], cc[4 * g4 + 3]);
+            for (int g = 0; g < 4; ++g)
+                if (8 * g + 4 * (lane >> 5) < CW)
+                    *(float4 *)(row + 8 * g) = make_float4(d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]);
         }
         __syncthreads();
         // taps of the rays whose positions fall in this chunk
 #pragma unroll
         for (int j = 0; j < AS; ++j) {
-            const int q = q0[j];
-            const bool t0 = q >= c0 && q < c0 + PCH;
-            const bool t1 = q + 1 >= c0 && q + 1 < c0 + PCH;
+            const int q = q0[j] - c0;
+            const bool t0 = q >= 0 && q < PCH;
+            const bool t1 = q >= -1 && q < PCH - 1;
             if (!(t0 || t1)) continue;
             const float a0 = t0 ? w0[j] : 0.f, a1 = t1 ? w1[j] : 0.f;
-            const float *Fj = fr + (j * Npi) * cstride + SF_PAD + (q - c0);   // slot of q
+            const float *F0 = fr + (q + 1) * CS + j * NPP;
 #pragma unroll
-            for (int r = 0; r < NPM; ++r) {
-                if (r < Npi) {
-                    const float x0 = Fj[r * cstride], x1 = Fj[r * cstride + 1];
-                    acc[j][r] = fmaf(a1, x1, fmaf(a0, x0, acc[j][r]));
-                }
+            for (int m = 0; m < NPP / 4; ++m) {
+                const float4 x0 = *(const float4 *)(F0 + 4 * m);
+                const float4 x1 = *(const float4 *)(F0 + CS + 4 * m);
+                acc[j][4 * m + 0] = fmaf(a1, x1.x, fmaf(a0, x0.x, acc[j][4 * m + 0]));
+                acc[j][4 * m + 1] = fmaf(a1, x1.y, fmaf(a0, x0.y, acc[j][4 * m + 1]));
+                acc[j][4 * m + 2] = fmaf(a1, x1.z, fmaf(a0, x0.z, acc[j][4 * m + 2]));
+                acc[j][4 * m + 3] = fmaf(a1, x1.w, fmaf(a0, x0.w, acc[j][4 * m + 3]));
             }
         }
     }
@@ -239,7 +225,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
         const int a = j < A ? gcls[grp * A + j] : -1;
         if (a < 0 || tid >= BT || b >= Ns) continue;
 #pragma unroll
-        for (int r = 0; r < NPM; ++r) {
+        for (int r = 0; r < NPP; ++r) {
             if (r >= Npi) continue;
             const int i = r * E.n0 + a;
             const int bo = (r & 1) ? Ns - 1 - b : b;
@@ -257,6 +243,26 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     if (E.part) {
         const double sum = block_sum(d2, sh);
         if (tid == 0) E.part[blockIdx.x] = sum;
+    }
+}
+
+// BF16 shadow of f: [Nz][N][N][K] FP32 -> [Nz][N][N][KP] BF16 (round to
+// nearest even), channels K..KP-1 zero.  One thread per 8 output channels.
+__global__ __launch_bounds__(NT) void k_to_bf16(const float *__restrict__ f,
+                                                __bf16 *__restrict__ out, size_t nvox, int K,
+                                                int KP)
+{
+    const int n8 = KP / 8;
+    const size_t total = nvox * n8;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * NT) {
+        const size_t v = e / n8;
+        const int k0 = (int)(e % n8) * 8;
+        const float *src = f + v * K;
+        v8bf o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = (__bf16)(k0 + q < K ? src[k0 + q] : 0.f);
+        *(v8bf *)(out + v * KP + k0) = o;
     }
 }
 
@@ -314,43 +320,31 @@ __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
     }
 }
 
-template <int NPM, int KB, int AS>
-static int launch_sf_t(const Plan &p, const float *f, const SfEpi &E, hipStream_t s, unsigned nb)
+template <int NPP, int KB, int AS>
+static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
 {
     const rt_geom &G = p.g;
     const SfCfg &C = p.sf;
-    auto kern = k_project_sf<NPM, KB, AS>;
+    auto kern = k_project_sf<NPP, KB, AS>;
     if (C.lds > 64 * 1024)
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)C.lds));
     KTimer kt("k_project_sf", s);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(ST), C.lds, s, f, p.d_phi, p.d_gcls_sf, p.d_gwalk_sf,
-                       p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, C.A, C.ngroups, C.BT, C.nbt,
-                       C.PCH, C.cstride, nb, E);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(ST), C.lds, s, (const __bf16 *)p.d_f16, p.d_phi,
+                       p.d_gcls_sf, p.d_gwalk_sf, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, C.A,
+                       C.ngroups, C.BT, C.nbt, C.PCH, C.CS, nb, E);
     kt.stop();
     return RT_OK;
 }
 
-template <int NPM, int KB>
-static int launch_sf_a(const Plan &p, const float *f, const SfEpi &E, hipStream_t s, unsigned nb)
+template <int NPP, int AS>
+static int launch_sf_k(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
 {
-    switch (p.sf.A) {
-    case 1: return launch_sf_t<NPM, KB, 1>(p, f, E, s, nb);
-    case 2: return launch_sf_t<NPM, KB, 2>(p, f, E, s, nb);
-    case 3: return launch_sf_t<NPM, KB, 3>(p, f, E, s, nb);
-    default: return launch_sf_t<NPM, KB, 4>(p, f, E, s, nb);
-    }
-}
-
-template <int NPM>
-static int launch_sf_k(const Plan &p, const float *f, const SfEpi &E, hipStream_t s, unsigned nb)
-{
-    switch ((p.g.K + 7) / 8) {
-    case 1: return launch_sf_a<NPM, 1>(p, f, E, s, nb);
-    case 2: return launch_sf_a<NPM, 2>(p, f, E, s, nb);
-    case 3:
-    case 4: return launch_sf_a<NPM, 4>(p, f, E, s, nb);
-    default: return launch_sf_a<NPM, 8>(p, f, E, s, nb);
+    switch (p.sf.KP / 16) {
+    case 1: return launch_sf_t<NPP, 1, AS>(p, E, s, nb);
+    case 2: return launch_sf_t<NPP, 2, AS>(p, E, s, nb);
+    case 3: return launch_sf_t<NPP, 3, AS>(p, E, s, nb);
+    default: return launch_sf_t<NPP, 4, AS>(p, E, s, nb);
     }
 }
 
@@ -358,8 +352,26 @@ static int launch_sf_k(const Plan &p, const float *f, const SfEpi &E, hipStream_
 
 unsigned sf_blocks(const Plan &p) { return (unsigned)p.g.Nz * p.sf.ngroups * p.sf.nbt; }
 
-int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
-                      float *h1, float sigma, double *part, hipStream_t s)
+int sf_slots(int npp) { return npp <= 8 ? 4 : npp <= 16 ? 2 : 1; }
+
+int launch_to_bf16(const Plan &p, const float *f, hipStream_t s)
+{
+    const rt_geom &G = p.g;
+    const size_t nvox = (size_t)G.Nz * G.N * G.N;
+    if (nvox == 0) return RT_OK;
+    const size_t total = nvox * (p.sf.KP / 8);
+    const unsigned nb = (unsigned)std::min<size_t>((total + NT - 1) / NT, 16384);
+    KTimer kt("k_to_bf16", s);
+    hipLaunchKernelGGL(k_to_bf16, dim3(nb), dim3(NT), 0, s, f, (__bf16 *)p.d_f16, nvox, G.K,
+                       p.sf.KP);
+    kt.stop();
+    RT_HIP(hipGetLastError());
+    ++p.shadow_gen;
+    return RT_OK;
+}
+
+int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, float *h1,
+                        float sigma, double *part, hipStream_t s)
 {
     const rt_geom &G = p.g;
     if (G.Nz == 0) return RT_OK;
@@ -373,15 +385,28 @@ int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const f
     E.Npi = G.Npi;
     const unsigned nb = sf_blocks(p);
     int rc;
-    const int npm = p.sf.NPM;
-    if (npm <= 4) rc = launch_sf_k<4>(p, f, E, s, nb);
-    else if (npm <= 8) rc = launch_sf_k<8>(p, f, E, s, nb);
-    else if (npm <= 12) rc = launch_sf_k<12>(p, f, E, s, nb);
-    else if (npm <= 16) rc = launch_sf_k<16>(p, f, E, s, nb);
-    else rc = launch_sf_k<32>(p, f, E, s, nb);
+    switch (p.sf.NPP) {
+    case 4: rc = launch_sf_k<4, 4>(p, E, s, nb); break;
+    case 8: rc = launch_sf_k<8, 4>(p, E, s, nb); break;
+    case 12: rc = launch_sf_k<12, 2>(p, E, s, nb); break;
+    case 16: rc = launch_sf_k<16, 2>(p, E, s, nb); break;
+    case 20: rc = launch_sf_k<20, 1>(p, E, s, nb); break;
+    case 24: rc = launch_sf_k<24, 1>(p, E, s, nb); break;
+    case 28: rc = launch_sf_k<28, 1>(p, E, s, nb); break;
+    default: rc = launch_sf_k<32, 1>(p, E, s, nb); break;
+    }
     if (rc) return rc;
     RT_HIP(hipGetLastError());
     return RT_OK;
+}
+
+int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
+                      float *h1, float sigma, double *part, hipStream_t s)
+{
+    if (p.g.Nz == 0) return RT_OK;
+    int rc = launch_to_bf16(p, f, s);
+    if (rc) return rc;
+    return launch_forward_sf16(p, g, mode, gdata, h1, sigma, part, s);
 }
 
 int launch_fold_mfma(const Plan &p, const float *g, hipStream_t s)

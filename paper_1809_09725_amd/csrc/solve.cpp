@@ -195,12 +195,22 @@ int step_job(Job &J, int n, hipStream_t s)
         double *pg = check ? p.d_part + off_grad(p) : nullptr;
         double *pd = check ? p.d_part + off_div(p) : nullptr;
         // step 3: h1 <- (h1 + sigma (R_T f~ - g)) / (1 + sigma)
-        if ((rc = launch_forward(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
+        if (p.form == RT_FORM_SF) {
+            // the BF16 shadow of f~ is current unless another call on the plan wrote it
+            if (J.shadow_gen != p.shadow_gen) {
+                if ((rc = launch_to_bf16(p, J.ft, s))) return rc;
+                J.shadow_gen = p.shadow_gen;
+            }
+            if ((rc = launch_forward_sf16(p, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
+        } else if ((rc = launch_forward(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) {
+            return rc;
+        }
         // step 4: h2 <- shrink(h2 + sigma grad S f~)
         if ((rc = launch_grad_shrink(p, J.Ff, J.h2, sigma, l1, l2, pg, s))) return rc;
         // steps 5-6: f+ = f - tau R_T* h1 + tau S^T div h2, f~ = 2 f+ - f
         if ((rc = launch_adjoint(p, J.h1, J.work, s))) return rc;
         if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s))) return rc;
+        J.shadow_gen = p.shadow_gen;
         ++J.iters;
         if (check && p.g.Nz > 0) {
             const int nbv = (int)voxel_blocks(p.g);
@@ -257,7 +267,7 @@ struct CkptHeader {
 
 }  // namespace
 
-extern "C" int rt_job_bytes(const rt_geom *geom, rt_form, rt_prec, size_t *bytes)
+extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec, size_t *bytes)
 {
     int rc = check_geom(geom);
     if (rc) return rc;
@@ -266,7 +276,8 @@ extern "C" int rt_job_bytes(const rt_geom *geom, rt_form, rt_prec, size_t *bytes
     const size_t tables = ((size_t)g.Ntheta * g.K + (size_t)g.Nt * g.K) * sizeof(float) +
                           (size_t)(g.Ntheta / g.Npi) * 2 * sizeof(double) + 64 * 1024;
     const size_t parts = ((size_t)1 << 18) * sizeof(double) + 16 * sizeof(double);
-    *bytes = tables + parts + plan_scratch_bytes(g) + n4_of(g) * sizeof(float) + job_state_bytes(g);
+    *bytes = tables + parts + plan_scratch_bytes(g) + n4_of(g) * sizeof(float) + job_state_bytes(g) +
+             (form == RT_FORM_SF ? shadow_bytes(g) : 0);
     return RT_OK;
 }
 
@@ -359,6 +370,7 @@ extern "C" int rt_job_restore(rt_job *job, const void *host_buf, void *stream)
     J.stopped = h.stopped != 0;
     J.tau = h.tau; J.sigma = h.sigma; J.L_R = h.L_R; J.L_G = h.L_G;
     J.residual = h.residual; J.objective = h.objective; J.rel_change = h.rel_change;
+    J.shadow_gen = ~0ull;   // the BF16 shadow no longer holds this f~
     return RT_OK;
 }
 

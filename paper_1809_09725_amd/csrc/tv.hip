@@ -179,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                                             const float *__restrict__ S, float lambda2,
                                             float *__restrict__ out, const float *__restrict__ adj,
                                             float *__restrict__ ft, float *__restrict__ Ff,
-                                            float tau, double *__restrict__ part, int N, int Nz,
+                                            float tau, double *__restrict__ part,
+                                            __bf16 *__restrict__ f16, int KP, int N, int Nz,
                                             int K, int Nt)
 {
     constexpr int KS = kstride(KT);
@@ -247,6 +248,18 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
             __syncthreads();
             if ((int)threadIdx.x < nv)
                 write_frames<KT>(rows + threadIdx.x * KS, sS, Ff, v, plane, Nt, K);
+            if (f16) {   // BF16 shadow of f~ for the synthesise-first projector
+                const int n8 = KP / 8;
+                for (int e = threadIdx.x; e < nv * n8; e += NT) {
+                    const int vl = e / n8, k0 = (e % n8) * 8;
+                    const float *row = rows + vl * KS;
+                    typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+                    v8bf o;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) o[q] = (__bf16)(k0 + q < K ? row[k0 + q] : 0.f);
+                    *(v8bf *)(f16 + (v0 + vl) * KP + k0) = o;
+                }
+            }
         }
     }
     if (MODE == 1 && part) {
@@ -348,24 +361,29 @@ int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, h
 template <int MODE>
 static void launch_div_t(const Plan &p, const float *pin, float lambda2, float *out,
                          const float *adj, float *ft, float *Ff, float tau, double *part,
-                         hipStream_t s)
+                         __bf16 *f16, hipStream_t s)
 {
     const unsigned nb = voxel_blocks(p.g);
     const size_t lds = tv_lds(p);
     const rt_geom &g = p.g;
+    const int KP = p.sf.KP;
+#define RT_DIV(KT) hipLaunchKernelGGL((k_div<KT, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, \
+                                      lambda2, out, adj, ft, Ff, tau, part, f16, KP, g.N, g.Nz,   \
+                                      g.K, g.Nt)
     switch (p.tv.KT) {
-    case 8: hipLaunchKernelGGL((k_div<8, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
-    case 16: hipLaunchKernelGGL((k_div<16, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
-    case 32: hipLaunchKernelGGL((k_div<32, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
-    default: hipLaunchKernelGGL((k_div<64, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, lambda2, out, adj, ft, Ff, tau, part, g.N, g.Nz, g.K, g.Nt); break;
+    case 8: RT_DIV(8); break;
+    case 16: RT_DIV(16); break;
+    case 32: RT_DIV(32); break;
+    default: RT_DIV(64); break;
     }
+#undef RT_DIV
 }
 
 int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hipStream_t s)
 {
     if (p.g.Nz == 0) return RT_OK;
     KTimer kt("k_tv_div", s);
-    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, s);
+    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, s);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
@@ -376,9 +394,11 @@ int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f
 {
     if (p.g.Nz == 0) return RT_OK;
     KTimer kt("k_div_update", s);
-    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, s);
+    __bf16 *f16 = p.form == RT_FORM_SF ? (__bf16 *)p.d_f16 : nullptr;
+    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, f16, s);
     kt.stop();
     RT_HIP(hipGetLastError());
+    if (f16) ++p.shadow_gen;
     return RT_OK;
 }
 

@@ -1,0 +1,134 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times.
+
+Slices are independent under parallel-beam geometry, so the operators are
+checked slice by slice: a few sampled slices carry seeded random data and are
+compared with the FP64 oracle on that slice alone; every other slice is zero
+and must come out exactly zero (no cross-slice leakage).  The 2048^2 slab,
+whose slices the oracle cannot finish in seconds, is checked on properties
+that hold at any size: the adjoint identity in FP64, agreement of the two
+forms, and the zero slices."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1809_09725_amd import inputs, rt4d
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+C2 = rt4d.Geom(N=512, Nz=128, Ns=512, Ntheta=1800, Npi=10, K=16, Nt=10)
+C3 = rt4d.Geom(N=1024, Nz=64, Ns=1024, Ntheta=3600, Npi=12, K=16, Nt=12)
+C5 = rt4d.Geom(N=2048, Nz=32, Ns=2048, Ntheta=3600, Npi=12, K=32, Nt=12)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def slice_geom(G):
+    return O.Geom(N=G.N, Nz=1, Ns=G.Ns, Ntheta=G.Ntheta, Npi=G.Npi, K=G.K, Nt=G.Nt)
+
+
+def sparse_f(G, zs, seed):
+    f = torch.zeros(G.f_shape, device=DEV)
+    host = {}
+    for z in zs:
+        h = inputs.uniform((G.N, G.N, G.K), seed + z)
+        host[z] = h
+        f[z].copy_(torch.from_numpy(h))
+    return f, host
+
+
+def sparse_g(G, zs, seed):
+    g = torch.zeros(G.g_shape, device=DEV)
+    host = {}
+    for z in zs:
+        h = inputs.uniform((G.Ntheta, G.Ns), seed + z)
+        host[z] = h
+        g[:, z, :].copy_(torch.from_numpy(h))
+    return g, host
+
+
+def others_zero_forward(g, zs):
+    mask = torch.ones(g.shape[1], dtype=torch.bool, device=DEV)
+    mask[list(zs)] = False
+    return bool((g[:, mask, :] == 0).all().item())
+
+
+def others_zero_adjoint(f, zs):
+    mask = torch.ones(f.shape[0], dtype=torch.bool, device=DEV)
+    mask[list(zs)] = False
+    return bool((f[mask] == 0).all().item())
+
+
+def check_sampled(G, form, prec, zf, za, tol):
+    torch.cuda.set_device(DEV)
+    plan = rt4d.Plan(G, form=form, prec=prec)
+    og = slice_geom(G)
+    f, fh = sparse_f(G, zf, 11)
+    g = plan.forward(f)
+    torch.cuda.synchronize()
+    assert others_zero_forward(g, zf)
+    for z in zf:
+        ref = O.forward(og, fh[z][None])[:, 0, :]
+        e = rel(g[:, z, :].cpu().numpy(), ref)
+        print(f"forward slice {z}: rel {e:.3e}", flush=True)
+        assert e <= tol
+    del f, g
+    gi, gh = sparse_g(G, za, 23)
+    fo = plan.adjoint(gi)
+    torch.cuda.synchronize()
+    assert others_zero_adjoint(fo, za)
+    for z in za:
+        ref = O.adjoint(og, gh[z][:, None, :])[0]
+        e = rel(fo[z].cpu().numpy(), ref)
+        print(f"adjoint slice {z}: rel {e:.3e}", flush=True)
+        assert e <= tol
+    plan.close()
+
+
+def test_c2_plain_sampled_slices():
+    check_sampled(C2, rt4d.RT_FORM_PF, rt4d.RT_PREC_FP32, (0, 77, 127), (0, 127), 1e-5)
+
+
+def test_c2_precision_sampled_slices():
+    check_sampled(C2, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA, (5,), (5,), 3e-3)
+
+
+def test_c3_precision_sampled_slice():
+    check_sampled(C3, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA, (63,), (0,), 3e-3)
+
+
+def test_c5_properties():
+    """2048^2 x 32 slab, K = 32: adjoint identity in FP64, precision vs plain
+    form, exact zeros in the empty slices."""
+    torch.cuda.set_device(DEV)
+    G = C5
+    zs = (0, 31)
+    f, _ = sparse_f(G, zs, 31)
+    g, _ = sparse_g(G, zs, 37)
+    pf = rt4d.Plan(G, form=rt4d.RT_FORM_PF, prec=rt4d.RT_PREC_FP32)
+    Rf = pf.forward(f)
+    Rg = pf.adjoint(g)
+    torch.cuda.synchronize()
+    assert others_zero_forward(Rf, zs) and others_zero_adjoint(Rg, zs)
+    lhs = rt4d.rt_dot(Rf, g)
+    rhs = rt4d.rt_dot(f, Rg)
+    scale = np.sqrt(rt4d.rt_dot(Rf, Rf) * rt4d.rt_dot(g, g))
+    print(f"adjoint identity: |lhs-rhs|/scale = {abs(lhs - rhs) / scale:.3e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * scale   # Cauchy-Schwarz on the FP32 operator bar
+    del Rg
+    pf.close()
+    sf = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    Rf16 = sf.forward(f)
+    torch.cuda.synchronize()
+    assert others_zero_forward(Rf16, zs)
+    d = torch.linalg.vector_norm((Rf16 - Rf).double()) / torch.linalg.vector_norm(Rf.double())
+    print(f"precision vs plain forward: rel {d.item():.3e}", flush=True)
+    assert d.item() <= 3e-3
+    sf.close()
