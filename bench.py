@@ -14,6 +14,11 @@ per iteration), inputs resident in HBM.  Prints one JSON line on stdout.
 
   python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
   python bench.py --copy-calib     # plain copy kernel for counter calibration
+  python bench.py --form sf        # the precision form on the same workload
+  python bench.py --serve [--jobs 64 --rate 2 --iters 60]
+        # serving form: a Poisson trace of jobs of mixed size served with the
+        # precision form under continuous batching, against the plain FP32
+        # solver one job at a time; prints its own JSON line
 """
 from __future__ import annotations
 
@@ -132,6 +137,71 @@ def copy_calib():
     print(json.dumps({"copy_calib_bytes_per_direction": 4 * n, "dispatches": 3}))
 
 
+def serve_main(args) -> int:
+    """Serving form: the C4 trace of Poisson-arriving jobs, served with the
+    precision form under continuous batching, against the plain FP32 solver
+    run one job at a time in arrival order on the same trace."""
+    import torch
+
+    from paper_1809_09725_amd import inputs, serving
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    trace = serving.c4_trace(n_jobs=args.jobs, rate=args.rate, seed=4, n_iter=args.iters)
+    log(f"trace: {len(trace)} jobs over {trace[-1].arrival:.1f} s, {args.iters} iterations each")
+    payloads = {}
+    t0 = time.perf_counter()
+    for s in trace:     # each job's sinogram, made before the clock starts (the request payload)
+        ph = inputs.make_phantom(s.N, s.Nz, s.Npi, 12, seed=4000 + s.jid,
+                                 axis_range=(s.N / 64, s.N / 16),
+                                 z_axis_range=(max(1.0, s.Nz / 16), max(1.0, s.Nz / 4)),
+                                 rho_range=(0.1, 0.5), speed_per_halfturn=s.N / 64)
+        g = inputs.sinogram(ph, s.N, s.Nz, s.Ns, s.Ntheta, s.Npi, noise=0.01, seed=4000 + s.jid,
+                            device="cuda")
+        payloads[s.jid] = g.float().cpu()
+        del g
+        log(f"payload {s.jid}: N={s.N} Nz={s.Nz} K={s.K} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    payload = lambda s: payloads[s.jid]
+    free, total = torch.cuda.mem_get_info(dev)
+    budget = int(args.budget_gb * 2**30) if args.budget_gb > 0 else int(0.8 * free)
+    log(f"HBM budget {budget / 2**30:.1f} GiB of {total / 2**30:.1f} GiB")
+
+    be = serving.GpuBackend(payload, form="sf")
+    sched = serving.Scheduler(be, budget, max_active=args.max_active, depth=2,
+                              window=args.window, sf=True)
+    recs_s, st_s = sched.run(trace)
+    be.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"served: {json.dumps(st_s)}")
+    recs_p, st_p, _ = serving.serial_baseline(trace, payload)
+    log(f"plain serial: {json.dumps(st_p)}")
+    # equal accuracy: final objectives of the two runs of every job
+    dobj = [abs(a.report["objective"] - b.report["objective"]) / abs(b.report["objective"])
+            for a, b in zip(recs_s, recs_p)]
+    out = {
+        "metric": "served p50/p99 latency vs plain; jobs/hour",
+        "unit": "jobs/hour", "value": round(st_s["jobs_per_hour"], 2),
+        "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": f"{len(trace)} jobs, Poisson arrivals {args.rate}/s, N in "
+                               "{256,512,1024}, Nz in {8,32,128}, K in {8,16,32}, Ntheta = 4N over "
+                               f"8 half-turns, {args.iters} iterations each, 12 moving ellipsoids, "
+                               "1% noise",
+                   "budget_gib": round(budget / 2**30, 1), "max_active": args.max_active,
+                   "window": args.window},
+        "served": {"form": "SF (bf16 contraction, fp32 projection)", **{k: round(v, 3) for k, v in st_s.items()}},
+        "plain_serial": {"form": "PF fp32, one job at a time", **{k: round(v, 3) for k, v in st_p.items()}},
+        "jobs_per_hour_vs_plain": round(st_s["jobs_per_hour"] / st_p["jobs_per_hour"], 3),
+        "p50_vs_plain": round(st_s["p50_latency_s"] / st_p["p50_latency_s"], 3),
+        "p99_vs_plain": round(st_s["p99_latency_s"] / st_p["p99_latency_s"], 3),
+        "objective_rel_diff_max": float(f"{max(dobj):.3e}"),
+        "objective_rel_diff_median": float(f"{sorted(dobj)[len(dobj) // 2]:.3e}"),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +215,16 @@ def main() -> int:
     ap.add_argument("--kernels-only", action="store_true",
                     help="uniform random sinogram instead of the phantom (same kernels and "
                          "launch shapes; fewer auxiliary launches, for counter runs)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving form: served precision-form trace vs the plain solver serial")
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=2.0)
+    ap.add_argument("--iters", type=int, default=60)
+    ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--window", type=int, default=2,
+                    help="jobs with the least remaining work that get iterations queued at once")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="HBM budget for resident jobs (default: 80%% of free device memory)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,6 +235,8 @@ def main() -> int:
     if args.copy_calib:
         copy_calib()
         return 0
+    if args.serve:
+        return serve_main(args)
 
     import torch
 

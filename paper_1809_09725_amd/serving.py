@@ -10,10 +10,12 @@ fixed number of iterations through the rt_job API of librt4d.  The loop
     `starve_s` seconds;
   * keeps every admitted job's f_k, duals and sinogram resident in device
     memory, each job on its own stream (default priority);
-  * interleaves iterations of the co-resident jobs: every job may have up to
-    `depth` iterations queued on the device, and jobs with the least
-    remaining work are topped up first, so short jobs overtake long ones
-    while long ones still keep the device busy;
+  * interleaves iterations of the co-resident jobs: the `window` jobs with
+    the least remaining work (shortest remaining processing time first) may
+    each have up to `depth` iterations queued on the device, so short jobs
+    overtake long ones while two or three jobs together keep the device
+    busy; the device has no notion of priority, so the host does the
+    ordering by what it queues;
   * runs the setup of a job (plan tables, power iteration for the step size)
     on a worker thread, so that admission never stalls the issue loop.
 
@@ -145,13 +147,14 @@ class Scheduler:
     """Continuous batching of solver iterations under an HBM budget."""
 
     def __init__(self, backend, budget_bytes: int, max_active: int = 8, depth: int = 2,
-                 starve_s: float = 30.0, sf: bool = True):
-        if budget_bytes <= 0 or max_active < 1 or depth < 1:
-            raise ValueError("budget, max_active and depth must be positive")
+                 window: int = 2, starve_s: float = 30.0, sf: bool = True):
+        if budget_bytes <= 0 or max_active < 1 or depth < 1 or window < 1:
+            raise ValueError("budget, max_active, depth and window must be positive")
         self.be = backend
         self.budget = int(budget_bytes)
         self.max_active = max_active
         self.depth = depth
+        self.window = window
         self.starve_s = starve_s
         self.sf = sf
 
@@ -207,9 +210,10 @@ class Scheduler:
                     be.release(a.h)
                     used -= a.rec.bytes
                     active.remove(a)
-            # ---- issue: least remaining work first, up to `depth` queued per job
+            # ---- issue: the `window` jobs with least remaining work, `depth` queued each
             issued = False
-            for a in sorted(active, key=lambda a: (a.remaining(), a.spec.jid)):
+            order = sorted(active, key=lambda a: (a.remaining(), a.spec.jid))
+            for a in order[:self.window]:
                 while a.issued < a.spec.n_iter and a.issued - a.done < self.depth:
                     be.issue(a.h)
                     a.issued += 1

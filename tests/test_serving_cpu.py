@@ -110,3 +110,16 @@ def test_job_larger_than_budget_rejected():
         Scheduler(be, be.bytes_needed(s) - 1).run([s])
     with pytest.raises(ValueError):
         Scheduler(be, 0)
+
+
+def test_window_one_runs_shortest_remaining_first():
+    # all resident from the start; window = 1 runs them one at a time, shortest first
+    tr = [spec(0, 0.0, N=128, Nz=8, n_iter=10), spec(1, 0.0, N=32, Nz=1, n_iter=10),
+          spec(2, 0.0, N=64, Nz=4, n_iter=10)]
+    be = FakeBackend(cost)
+    recs, _ = Scheduler(be, 1 << 40, max_active=8, window=1).run(tr)
+    fin = {r.jid: r.finished for r in recs}
+    assert fin[1] < fin[2] < fin[0]
+    # strictly one job's iterations at a time
+    seq = be.order
+    assert seq == sorted(seq, key=lambda j: [1, 2, 0].index(j))
