@@ -40,7 +40,7 @@ PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9           # 78.6 TFLOP/s
 KERNELS = ("k_project", "k_contract", "k_fold", "k_backproject", "k_grad_shrink",
            "k_div_update", "k_project_sf", "k_fold_mfma")
 SOURCES = {"k_project": "proj_pf.hip", "k_contract": "proj_pf.hip", "k_fold": "proj_pf.hip",
-           "k_backproject": "proj_pf.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip",
+           "k_backproject": "backproject.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip",
            "k_project_sf": "proj_sf.hip", "k_fold_mfma": "proj_sf.hip"}
 
 

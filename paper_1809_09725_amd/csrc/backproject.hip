@@ -1,0 +1,174 @@
+// Pixel-driven back-projection of the folded sinogram g~ (Sec. 4, eq.
+// radadjapr): out_k(z,r,q) = sum_a sum_b w(theta0_a, b, q, r) g~(a,z,b,k), the
+// exact transpose of the ray-driven forward projection: the weight of bin b
+// for pixel p is max(0, 1 - |s_b - s_p| / c) / c with c = max(|cos|, |sin|),
+// Joseph's linear interpolation written from the pixel's side.
+//
+// A 32x32 pixel tile takes the classes in rounds of CA; each round stages in
+// LDS the window of detector bins the tile's pixels reach for each class
+// (all KC channels of a bin in one row), then every pixel takes the two bins
+// around its s_p for each class.  Positions in FP64, weights and sums in FP32.
+#include "common.h"
+#include "internal.h"
+
+namespace rt {
+namespace {
+
+constexpr int BP_VPT = 4;     // pixels per thread (rows 8 apart)
+constexpr int BP_MAXCA = 16;  // classes staged per round, at most
+
+template <int KC, int VEC>
+__global__ __launch_bounds__(NT, 2) void k_backproject(
+    const float *__restrict__ gt, float *__restrict__ out, const double *__restrict__ ccos,
+    const double *__restrict__ csin, int N, int Nz, int Ns, int K, int n0, int nkc, int ntq,
+    int ntr, int CA, int WMAX, int stride, unsigned nblocks)
+{
+    extern __shared__ float win[];   // [CA][WMAX][stride]
+    __shared__ int s_wlo[BP_MAXCA], s_w[BP_MAXCA];
+    __shared__ float s_inv[BP_MAXCA];   // 1 / max(|cos|, |sin|) of the staged classes
+    unsigned lid = xcd_remap(blockIdx.x, nblocks);
+    const int tq = lid % ntq;
+    lid /= ntq;
+    const int tr = lid % ntr;
+    lid /= ntr;
+    const int kc = lid % nkc;
+    const int z = lid / nkc;
+    const int tid = threadIdx.x;
+    const int k0 = kc * KC;
+    const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
+
+    const int q = tq * 32 + (tid & 31);
+    const double x = (double)q - hN;
+    double y[BP_VPT];
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j) y[j] = (double)(tr * 32 + (tid >> 5) + 8 * j) - hN;
+    const double xlo = (double)(tq * 32) - hN, xhi = xlo + 31.0;
+    const double ylo = (double)(tr * 32) - hN, yhi = ylo + 31.0;
+
+    float acc[BP_VPT][KC];
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[j][k] = 0.f;
+
+    for (int a0 = 0; a0 < n0; a0 += CA) {
+        const int nca = min(CA, n0 - a0);
+        __syncthreads();
+        if (tid < nca) {
+            // detector window of class a over the tile: s_p is affine in
+            // (x, y) and each rounding step is monotone, so the extreme
+            // positions of the tile's pixels are at its corners
+            const double cs = ccos[a0 + tid], sn = csin[a0 + tid];
+            const double u00 = fma(xlo, cs, fma(ylo, sn, hS));
+            const double u10 = fma(xhi, cs, fma(ylo, sn, hS));
+            const double u01 = fma(xlo, cs, fma(yhi, sn, hS));
+            const double u11 = fma(xhi, cs, fma(yhi, sn, hS));
+            const double umin = fmin(fmin(u00, u10), fmin(u01, u11));
+            const double umax = fmax(fmax(u00, u10), fmax(u01, u11));
+            const int lo = (int)floor(umin);
+            s_wlo[tid] = lo;
+            s_w[tid] = (int)floor(umax) + 2 - lo;
+            s_inv[tid] = (float)(1.0 / fmax(fabs(cs), fabs(sn)));
+        }
+        __syncthreads();
+        if (VEC == 4) {
+            constexpr int NQ = KC / 4;
+            for (int e = tid; e < nca * WMAX * NQ; e += NT) {
+                const int c = e / (WMAX * NQ), r = e % (WMAX * NQ);
+                const int w = r / NQ, kq = r % NQ;
+                const int b = s_wlo[c] + w;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (w < s_w[c] && b >= 0 && b < Ns && k0 + 4 * kq < K)
+                    v = *(const float4 *)(gt + (((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + 4 * kq);
+                *(float4 *)(win + (c * WMAX + w) * stride + 4 * kq) = v;
+            }
+        } else {
+            for (int e = tid; e < nca * WMAX * KC; e += NT) {
+                const int c = e / (WMAX * KC), r = e % (WMAX * KC);
+                const int w = r / KC, kk = r % KC;
+                const int b = s_wlo[c] + w;
+                float v = 0.f;
+                if (w < s_w[c] && b >= 0 && b < Ns && k0 + kk < K)
+                    v = gt[(((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + kk];
+                win[(c * WMAX + w) * stride + kk] = v;
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < nca; ++c) {
+            const double cs = ccos[a0 + c], sn = csin[a0 + c];
+            const float invc = s_inv[c];
+            const int wlo = s_wlo[c];
+            const float *wc = win + c * WMAX * stride;
+#pragma unroll
+            for (int j = 0; j < BP_VPT; ++j) {
+                const double u = fma(x, cs, fma(y[j], sn, hS));   // s_p in bin units
+                const double fl = floor(u);
+                const float fr = (float)(u - fl);
+                // triangle weights of the bins floor(u) and floor(u)+1
+                const float w0 = fmaxf(0.f, 1.f - fr * invc) * invc;
+                const float w1 = fmaxf(0.f, 1.f - (1.f - fr) * invc) * invc;
+                const float *t0 = wc + ((int)fl - wlo) * stride;
+#pragma unroll
+                for (int k = 0; k < KC; k += 4) {
+                    const float4 x0 = *(const float4 *)(t0 + k);
+                    const float4 x1 = *(const float4 *)(t0 + stride + k);
+                    acc[j][k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, acc[j][k + 0]));
+                    acc[j][k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, acc[j][k + 1]));
+                    acc[j][k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, acc[j][k + 2]));
+                    acc[j][k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, acc[j][k + 3]));
+                }
+            }
+        }
+    }
+
+    if (q >= N) return;
+#pragma unroll
+    for (int j = 0; j < BP_VPT; ++j) {
+        const int r = tr * 32 + (tid >> 5) + 8 * j;
+        if (r >= N) continue;
+        float *dst = out + (((size_t)z * N + r) * N + q) * K + k0;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k0 + k < K) dst[k] = acc[j][k];
+    }
+}
+
+template <int KC, int VEC>
+static void launch_bp_t(const Plan &p, float *out, hipStream_t s, unsigned nb, int ntq, int ntr)
+{
+    const rt_geom &G = p.g;
+    const AdjCfg &B = p.adj;
+    KTimer kt("k_backproject", s);
+    hipLaunchKernelGGL((k_backproject<KC, VEC>), dim3(nb), dim3(NT), B.lds, s, p.d_scr, out,
+                       p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, p.n0, B.nkc, ntq, ntr, B.CA,
+                       B.WMAX, B.stride, nb);
+    kt.stop();
+}
+
+}  // namespace
+
+int launch_backproject(const Plan &p, float *out, hipStream_t s)
+{
+    const rt_geom &G = p.g;
+    const AdjCfg &B = p.adj;
+    if (G.Nz == 0) return RT_OK;
+    const int ntq = (G.N + 31) / 32, ntr = (G.N + 31) / 32;
+    const unsigned nb = (unsigned)G.Nz * B.nkc * ntr * ntq;
+    if (B.vec == 4) {
+        switch (B.KC) {
+        case 4: launch_bp_t<4, 4>(p, out, s, nb, ntq, ntr); break;
+        case 8: launch_bp_t<8, 4>(p, out, s, nb, ntq, ntr); break;
+        default: launch_bp_t<16, 4>(p, out, s, nb, ntq, ntr); break;
+        }
+    } else {
+        switch (B.KC) {
+        case 4: launch_bp_t<4, 1>(p, out, s, nb, ntq, ntr); break;
+        case 8: launch_bp_t<8, 1>(p, out, s, nb, ntq, ntr); break;
+        default: launch_bp_t<16, 1>(p, out, s, nb, ntq, ntr); break;
+        }
+    }
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+}  // namespace rt
