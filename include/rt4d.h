@@ -81,8 +81,12 @@ typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1 } rt_form;
 
 /* RT_PREC_FP32: every product in FP32.  RT_PREC_BF16MFMA: the basis
  * contraction sum_k Phi f_k (and its transpose) in BF16 on the matrix cores
- * with FP32 accumulation (f_k rounded to BF16, Phi split into BF16 hi+lo),
- * the projection itself in FP32.  BF16 requires RT_FORM_SF. */
+ * with FP32 accumulation (f_k rounded to BF16 with round-to-nearest-even,
+ * Phi split into BF16 hi+lo), the projection itself in FP32.  BF16 requires
+ * RT_FORM_SF, and RT_FORM_SF requires BF16 and Npi <= 32.  An SF plan keeps a
+ * BF16 copy of the volume it last projected ([Nz][N][N][K rounded up to 16]);
+ * rt_forward converts its input into it, a job refreshes it in the primal
+ * update. */
 typedef enum { RT_PREC_FP32 = 0, RT_PREC_BF16MFMA = 1 } rt_prec;
 
 typedef struct rt_plan rt_plan;
@@ -162,7 +166,9 @@ int solve(const rt_plan *plan, const rt_solve_params *params, const float *g,
  * monitor every check_every iterations blocks for 40 bytes). */
 typedef struct rt_job rt_job;
 
-/* Device bytes one job of this geometry needs: plan + job state. */
+/* Device bytes one job of this geometry needs: plan (tables, scratch, and
+ * for RT_FORM_SF the BF16 copy of the volume) + job state.  The caller's g
+ * and f are not included. */
 int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec prec, size_t *bytes);
 int rt_job_create(const rt_plan *plan, const rt_solve_params *params, const float *g,
                   float *f, void *stream, rt_job **out);

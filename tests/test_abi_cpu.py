@@ -75,6 +75,12 @@ def test_job_bytes_accounts_for_state():
     state = (2 * nf + 2 * ng + 5 * n4) * 4
     scratch = 180 * 128 * 512 * 16 * 4 + n4 * 4
     assert state + scratch <= b <= state + scratch + 64 * 2 ** 20
+    # the precision form adds the BF16 shadow of f~ (K rounded up to 16 channels)
+    b16 = rt4d.rt_job_bytes(geom, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA)
+    assert b16 - b == 128 * 512 * 512 * 16 * 2
+    g5 = rt4d.Geom(N=64, Nz=2, Ns=64, Ntheta=80, Npi=8, K=5, Nt=8)
+    assert (rt4d.rt_job_bytes(g5, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA) -
+            rt4d.rt_job_bytes(g5)) == 2 * 64 * 64 * 16 * 2
 
 
 def test_null_handles():
