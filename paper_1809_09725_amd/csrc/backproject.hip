@@ -21,8 +21,9 @@ template <int KC, int VEC>
 __global__ __launch_bounds__(NT, 2) void k_backproject(
     const float *__restrict__ gt, float *__restrict__ out, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int n0, int nkc, int ntq,
-    int ntr, int CA, int WMAX, int stride, unsigned nblocks)
+    int ntr, int CA, int WMAX, unsigned nblocks)
 {
+    constexpr int stride = KC + 4;   // an odd number of 16-byte groups per bin
     extern __shared__ float win[];   // [CA][WMAX][stride]
     __shared__ int s_wlo[BP_MAXCA], s_w[BP_MAXCA];
     __shared__ float s_inv[BP_MAXCA];   // 1 / max(|cos|, |sin|) of the staged classes
@@ -39,9 +40,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
 
     const int q = tq * 32 + (tid & 31);
     const double x = (double)q - hN;
-    double y[BP_VPT];
-#pragma unroll
-    for (int j = 0; j < BP_VPT; ++j) y[j] = (double)(tr * 32 + (tid >> 5) + 8 * j) - hN;
+    const double y0 = (double)(tr * 32 + (tid >> 5)) - hN;   // rows y0 + 8j, j < BP_VPT
     const double xlo = (double)(tq * 32) - hN, xhi = xlo + 31.0;
     const double ylo = (double)(tr * 32) - hN, yhi = ylo + 31.0;
 
@@ -65,9 +64,11 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             const double u11 = fma(xhi, cs, fma(yhi, sn, hS));
             const double umin = fmin(fmin(u00, u10), fmin(u01, u11));
             const double umax = fmax(fmax(u00, u10), fmax(u01, u11));
-            const int lo = (int)floor(umin);
+            // one spare bin on each side: a pixel's s_p, formed incrementally
+            // over its rows, may round an ulp outside [umin, umax]
+            const int lo = (int)floor(umin) - 1;
             s_wlo[tid] = lo;
-            s_w[tid] = (int)floor(umax) + 2 - lo;
+            s_w[tid] = (int)floor(umax) + 3 - lo;
             s_inv[tid] = (float)(1.0 / fmax(fabs(cs), fabs(sn)));
         }
         __syncthreads();
@@ -97,17 +98,18 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
         for (int c = 0; c < nca; ++c) {
             const double cs = ccos[a0 + c], sn = csin[a0 + c];
             const float invc = s_inv[c];
-            const int wlo = s_wlo[c];
-            const float *wc = win + c * WMAX * stride;
+            const int cw = c * WMAX - s_wlo[c];   // window row of bin b: cw + b
+            // s_p in bin units for the thread's first row; rows 8 apart add 8 sin
+            const double u0 = fma(x, cs, fma(y0, sn, hS)), du = 8.0 * sn;
 #pragma unroll
             for (int j = 0; j < BP_VPT; ++j) {
-                const double u = fma(x, cs, fma(y[j], sn, hS));   // s_p in bin units
+                const double u = u0 + (double)j * du;
                 const double fl = floor(u);
                 const float fr = (float)(u - fl);
                 // triangle weights of the bins floor(u) and floor(u)+1
                 const float w0 = fmaxf(0.f, 1.f - fr * invc) * invc;
                 const float w1 = fmaxf(0.f, 1.f - (1.f - fr) * invc) * invc;
-                const float *t0 = wc + ((int)fl - wlo) * stride;
+                const float *t0 = win + (cw + (int)fl) * stride;
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {
                     const float4 x0 = *(const float4 *)(t0 + k);
@@ -141,7 +143,7 @@ static void launch_bp_t(const Plan &p, float *out, hipStream_t s, unsigned nb, i
     KTimer kt("k_backproject", s);
     hipLaunchKernelGGL((k_backproject<KC, VEC>), dim3(nb), dim3(NT), B.lds, s, p.d_scr, out,
                        p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, p.n0, B.nkc, ntq, ntr, B.CA,
-                       B.WMAX, B.stride, nb);
+                       B.WMAX, nb);
     kt.stop();
 }
 

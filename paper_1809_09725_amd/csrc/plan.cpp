@@ -103,23 +103,6 @@ static void build_tables(const rt_geom &g, const double *phi, const double *S, T
     }
 }
 
-static int pick_kc(int K, int positions, size_t budget, int *KC, int *stride)
-{
-    const int K4 = (K + 3) / 4 * 4;
-    for (int kc : {16, 8, 4}) {
-        if (kc > K4 && kc != 4) continue;
-        for (int pad : {4, 0}) {
-            const size_t need = (size_t)positions * (kc + pad) * sizeof(float);
-            if (need <= budget) {
-                *KC = kc;
-                *stride = kc + pad;
-                return 0;
-            }
-        }
-    }
-    return -1;
-}
-
 static int configure(Plan &p)
 {
     const rt_geom &g = p.g;
@@ -171,11 +154,19 @@ static int configure(Plan &p)
     int wmax = 2;
     for (int a = 0; a < n0; ++a) {
         const double span = (B.TQ - 1) * std::fabs(p.T.ccos[a]) + (B.TR - 1) * std::fabs(p.T.csin[a]);
-        wmax = std::max(wmax, (int)std::ceil(span) + 4);
+        wmax = std::max(wmax, (int)std::ceil(span) + 6);
     }
     B.WMAX = wmax;
-    if (pick_kc(g.K, B.CA * B.WMAX, budget, &B.KC, &B.stride))
-        return fail(RT_E_SHAPE, "back-projection staging does not fit");
+    // KC channels per window row, stride KC + 4 floats (an odd number of
+    // 16-byte groups); fewer classes per round when the window is wide
+    {
+        const int K4 = (g.K + 3) / 4 * 4;
+        B.KC = K4 >= 16 ? 16 : K4 >= 8 ? 8 : 4;
+        B.stride = B.KC + 4;
+        while (B.CA > 1 && (size_t)B.CA * B.WMAX * B.stride * sizeof(float) > budget) B.CA /= 2;
+        if ((size_t)B.CA * B.WMAX * B.stride * sizeof(float) > budget)
+            return fail(RT_E_SHAPE, "back-projection staging does not fit");
+    }
     B.nkc = (g.K + B.KC - 1) / B.KC;
     B.vec = (g.K % 4 == 0) ? 4 : 1;
     B.lds = (size_t)B.CA * B.WMAX * B.stride * sizeof(float);
