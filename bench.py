@@ -167,15 +167,15 @@ def serve_main(args) -> int:
     budget = int(args.budget_gb * 2**30) if args.budget_gb > 0 else int(0.8 * free)
     log(f"HBM budget {budget / 2**30:.1f} GiB of {total / 2**30:.1f} GiB")
 
-    be = serving.GpuBackend(payload, form="sf")
+    be = serving.GpuBackend(payload, form=args.serve_form)
     sched = serving.Scheduler(be, budget, max_active=args.max_active, depth=2,
-                              window=args.window, sf=True)
+                              window=args.window, form=args.serve_form, log=log)
     recs_s, st_s = sched.run(trace)
     be.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log(f"served: {json.dumps(st_s)}")
-    recs_p, st_p, _ = serving.serial_baseline(trace, payload)
+    recs_p, st_p, _ = serving.serial_baseline(trace, payload, log=log)
     log(f"plain serial: {json.dumps(st_p)}")
     # equal accuracy: final objectives of the two runs of every job
     dobj = [abs(a.report["objective"] - b.report["objective"]) / abs(b.report["objective"])
@@ -190,7 +190,11 @@ def serve_main(args) -> int:
                                "1% noise",
                    "budget_gib": round(budget / 2**30, 1), "max_active": args.max_active,
                    "window": args.window},
-        "served": {"form": "SF (bf16 contraction, fp32 projection)", **{k: round(v, 3) for k, v in st_s.items()}},
+        "served": {"form": {"auto": "per job: SF (bf16 contraction, fp32 projection) when K > Npi, "
+                                    "else PF fp32", "sf": "SF (bf16 contraction, fp32 projection)",
+                            "pf": "PF fp32"}[args.serve_form],
+                   "jobs_sf": sum(serving.pick_form(s, args.serve_form) == "sf" for s in trace),
+                   **{k: round(v, 3) for k, v in st_s.items()}},
         "plain_serial": {"form": "PF fp32, one job at a time", **{k: round(v, 3) for k, v in st_p.items()}},
         "jobs_per_hour_vs_plain": round(st_s["jobs_per_hour"] / st_p["jobs_per_hour"], 3),
         "p50_vs_plain": round(st_s["p50_latency_s"] / st_p["p50_latency_s"], 3),
@@ -221,6 +225,9 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=2.0)
     ap.add_argument("--iters", type=int, default=60)
     ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--serve-form", choices=("auto", "sf", "pf"), default="auto",
+                    help="form of the served jobs: auto = precision form when K > Npi, plain "
+                         "FP32 otherwise")
     ap.add_argument("--window", type=int, default=2,
                     help="jobs with the least remaining work that get iterations queued at once")
     ap.add_argument("--budget-gb", type=float, default=0.0,

@@ -20,6 +20,8 @@
 namespace rt {
 namespace {
 
+constexpr int ZC = 4;   // consecutive slices per work item of the gradient and divergence
+
 // LDS row stride (floats) of one voxel's K values: odd, so that 32
 // consecutive voxels read with ds_read_b32 hit 32 different banks.
 __host__ __device__ constexpr int kstride(int KT) { return KT + 1; }
@@ -122,15 +124,20 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
                                              double *__restrict__ part, int N, int Nz, int Nt)
 {
     __shared__ double sh[NT / 64];
-    const size_t plane = (size_t)N * N, nvox = plane * Nz;
+    const size_t plane = (size_t)N * N;
+    const size_t nitem = plane * ((Nz + ZC - 1) / ZC);
     double tvs = 0.0;
-    for (size_t v = (size_t)blockIdx.x * NT + threadIdx.x; v < nvox; v += (size_t)gridDim.x * NT) {
-        const int q = (int)(v % N);
-        const int r = (int)((v / N) % N);
-        const size_t z = v / plane, pv = v % plane;
-        const bool hx = q < N - 1, hy = r < N - 1, hz = (int)z < Nz - 1;
-        const float *Fz = F + z * Nt * plane + pv;
-        float *pz = (MODE != 2) ? p + z * Nt * 4 * plane + pv : nullptr;
+    // a work item is one (row, column) over ZC consecutive slices, so the
+    // z-neighbour frames one slice reads are still in L2 when the next one
+    // reads them as its own
+    for (size_t it = (size_t)blockIdx.x * NT + threadIdx.x; it < nitem; it += (size_t)gridDim.x * NT)
+    for (int z = (int)(it / plane) * ZC, ze = min(Nz, z + ZC); z < ze; ++z) {
+        const size_t pv = it % plane;
+        const int q = (int)(pv % N);
+        const int r = (int)(pv / N);
+        const bool hx = q < N - 1, hy = r < N - 1, hz = z < Nz - 1;
+        const float *Fz = F + (size_t)z * Nt * plane + pv;
+        float *pz = (MODE != 2) ? p + (size_t)z * Nt * 4 * plane + pv : nullptr;
         float F0 = Fz[0];
         for (int m = 0; m < Nt; ++m) {
             const float *Fm = Fz + (size_t)m * plane;
@@ -189,10 +196,17 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
     float *rows = sm + Nt * KT;              // [NT][KS]
     __shared__ double sh[NT / 64];
     stage_S<KT>(S, K, Nt, sS);
-    const size_t plane = (size_t)N * N, nvox = plane * Nz;
+    const size_t plane = (size_t)N * N;
+    const size_t ntile = (plane + NT - 1) / NT;
+    const size_t ntask = ntile * ((Nz + ZC - 1) / ZC);
     double dn2 = 0.0, fn2 = 0.0;
-    for (size_t v0 = (size_t)blockIdx.x * NT; v0 < nvox; v0 += (size_t)gridDim.x * NT) {
-        const int nv = (int)std::min<size_t>(NT, nvox - v0);
+    // a task is NT consecutive voxels of a plane over ZC consecutive slices
+    // (the z-neighbour plane of h2 is then still in L2)
+    for (size_t task = blockIdx.x; task < ntask; task += gridDim.x)
+    for (int zz = (int)(task / ntile) * ZC, ze = min(Nz, zz + ZC); zz < ze; ++zz) {
+        const size_t pv0 = (task % ntile) * NT;
+        const size_t v0 = (size_t)zz * plane + pv0;
+        const int nv = (int)std::min<size_t>(NT, plane - pv0);
         const size_t v = v0 + threadIdx.x;
         __syncthreads();   // S staged; the previous chunk is done with rows
         if ((int)threadIdx.x < nv) {

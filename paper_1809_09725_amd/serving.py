@@ -147,7 +147,7 @@ class Scheduler:
     """Continuous batching of solver iterations under an HBM budget."""
 
     def __init__(self, backend, budget_bytes: int, max_active: int = 8, depth: int = 2,
-                 window: int = 2, starve_s: float = 30.0, sf: bool = True):
+                 window: int = 2, starve_s: float = 30.0, form: str = "sf", log=None):
         if budget_bytes <= 0 or max_active < 1 or depth < 1 or window < 1:
             raise ValueError("budget, max_active, depth and window must be positive")
         self.be = backend
@@ -155,8 +155,9 @@ class Scheduler:
         self.max_active = max_active
         self.depth = depth
         self.window = window
+        self.log = log           # called with a line per finished job
         self.starve_s = starve_s
-        self.sf = sf
+        self.form = form         # for the work estimate of each job
 
     def run(self, trace: list[JobSpec]) -> tuple[list[Record], dict]:
         be = self.be
@@ -188,7 +189,8 @@ class Scheduler:
                     used += need
                     rec = records[s.jid]
                     rec.admitted, rec.bytes = be.now() - t0, need
-                    setting_up.append(_Active(s, be.start_admit(s), s.work_per_iter(self.sf), rec))
+                    est = s.work_per_iter(pick_form(s, self.form) == "sf")
+                    setting_up.append(_Active(s, be.start_admit(s), est, rec))
                     n_res += 1
                     continue
                 if i == 0 and now - s.arrival >= self.starve_s:
@@ -210,6 +212,11 @@ class Scheduler:
                     be.release(a.h)
                     used -= a.rec.bytes
                     active.remove(a)
+                    if self.log:
+                        s = a.spec
+                        self.log(f"served job {s.jid} (N={s.N} Nz={s.Nz} K={s.K}) done at "
+                                 f"{a.rec.finished:.1f} s, latency {a.rec.latency:.1f} s, "
+                                 f"{len(active)} active, {len(waiting)} waiting")
             # ---- issue: the `window` jobs with least remaining work, `depth` queued each
             issued = False
             order = sorted(active, key=lambda a: (a.remaining(), a.spec.jid))
@@ -238,19 +245,31 @@ class _Slot:
         self.plan = self.job = self.g = self.f = None
 
 
+def pick_form(s: JobSpec, form: str) -> str:
+    """'sf' or 'pf' for one job.  'auto' takes the synthesise-first precision
+    form when K > Npi: per ray and line it taps Npi frames (plus writing the
+    frames once) where project-first taps K channels, so it wins only when
+    the job has more basis functions than half-turns."""
+    if form == "auto":
+        return "sf" if s.K > s.Npi else "pf"
+    return form
+
+
 class GpuBackend:
     """Runs jobs through librt4d on one GPU.  `payload(spec)` returns the
-    job's sinogram as a host (preferably pinned) FP32 tensor."""
+    job's sinogram as a host (preferably pinned) FP32 tensor.  form: 'sf'
+    (precision), 'pf' (plain FP32) or 'auto' (per job, see pick_form)."""
 
     def __init__(self, payload, form: str = "sf", device: int = 0, n_pow: int = 20,
                  keep_results: bool = False, setup_threads: int = 2, poll_s: float = 2e-4):
         import torch
 
         from . import rt4d
+        if form not in ("sf", "pf", "auto"):
+            raise ValueError(form)
         self.torch, self.rt = torch, rt4d
         self.payload = payload
-        self.form = rt4d.RT_FORM_SF if form == "sf" else rt4d.RT_FORM_PF
-        self.prec = rt4d.RT_PREC_BF16MFMA if form == "sf" else rt4d.RT_PREC_FP32
+        self.form_name = form
         self.dev = torch.device("cuda", device)
         self.n_pow = n_pow
         self.keep = keep_results
@@ -261,11 +280,17 @@ class GpuBackend:
     def now(self) -> float:
         return time.perf_counter()
 
+    def _form(self, s: JobSpec):
+        rt = self.rt
+        if pick_form(s, self.form_name) == "sf":
+            return rt.RT_FORM_SF, rt.RT_PREC_BF16MFMA
+        return rt.RT_FORM_PF, rt.RT_PREC_FP32
+
     def bytes_needed(self, s: JobSpec) -> int:
         G = s.geom()
         nf = G.Nz * G.N * G.N * G.K
         ng = G.Ntheta * G.Nz * G.Ns
-        return self.rt.rt_job_bytes(G, self.form, self.prec) + 4 * (nf + ng)
+        return self.rt.rt_job_bytes(G, *self._form(s)) + 4 * (nf + ng)
 
     def _setup(self, sl: _Slot) -> None:
         torch, rt = self.torch, self.rt
@@ -276,7 +301,8 @@ class GpuBackend:
             host = self.payload(s)
             sl.g = host.to(self.dev, non_blocking=True)
             sl.f = torch.zeros(G.f_shape, device=self.dev)
-            sl.plan = rt.Plan(G, form=self.form, prec=self.prec)
+            form, prec = self._form(s)
+            sl.plan = rt.Plan(G, form=form, prec=prec)
             sl.job = rt.Job(sl.plan, sl.g, sl.f, lambda1=s.lambda1, lambda2=s.lambda2,
                             n_iter=s.n_iter, n_pow=self.n_pow, check_every=0, seed=s.seed)
         sl.stream.synchronize()
@@ -329,7 +355,7 @@ class GpuBackend:
 
 
 def serial_baseline(trace: list[JobSpec], payload, device: int = 0, n_pow: int = 20,
-                    keep_results: bool = False) -> tuple[list[Record], dict, dict]:
+                    keep_results: bool = False, log=None) -> tuple[list[Record], dict, dict]:
     """The plain FP32 solver, one job at a time in arrival order: each job
     starts when it has arrived and the previous one has finished."""
     import torch
@@ -357,6 +383,9 @@ def serial_baseline(trace: list[JobSpec], payload, device: int = 0, n_pow: int =
         rec.finished = time.perf_counter() - t0
         rec.iters = s.n_iter
         recs.append(rec)
+        if log:
+            log(f"plain job {s.jid} (N={s.N} Nz={s.Nz} K={s.K}) done at {rec.finished:.1f} s, "
+                f"latency {rec.latency:.1f} s")
     makespan = max(r.finished for r in recs) if recs else 0.0
     by_id = {r.jid: r for r in recs}
     ordered = [by_id[s.jid] for s in trace]

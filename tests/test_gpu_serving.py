@@ -3,7 +3,7 @@ import pytest
 import torch
 
 from paper_1809_09725_amd import inputs, rt4d
-from paper_1809_09725_amd.serving import GpuBackend, JobSpec, Scheduler, serial_baseline
+from paper_1809_09725_amd.serving import GpuBackend, JobSpec, Scheduler, pick_form, serial_baseline
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +34,12 @@ def alone(s, form):
     return f
 
 
-@pytest.mark.parametrize("form", ["sf", "pf"])
+@pytest.mark.parametrize("form", ["sf", "pf", "auto"])
 def test_served_equals_alone(form):
     torch.cuda.set_device(0)
     tr = tiny_trace()
     be = GpuBackend(payload, form=form, keep_results=True)
-    recs, st = Scheduler(be, 8 << 30, max_active=4, depth=2, sf=form == "sf").run(tr)
+    recs, st = Scheduler(be, 8 << 30, max_active=4, depth=2, form=form).run(tr)
     be.close()
     assert st["jobs"] == len(tr)
     # several jobs were resident together (the mix really overlapped)
@@ -47,7 +47,7 @@ def test_served_equals_alone(form):
     assert any(a[0] < b[1] and b[0] < a[1] for i, a in enumerate(spans) for b in spans[i + 1:])
     for s, r in zip(tr, recs):
         assert r.iters == s.n_iter
-        ref = alone(s, form)
+        ref = alone(s, pick_form(s, form))
         got = be.results[s.jid]
         # same kernels, same order, per-job scratch: the results agree bitwise
         assert torch.equal(got, ref), f"job {s.jid}: max diff {(got - ref).abs().max().item()}"

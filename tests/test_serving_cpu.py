@@ -123,3 +123,10 @@ def test_window_one_runs_shortest_remaining_first():
     # strictly one job's iterations at a time
     seq = be.order
     assert seq == sorted(seq, key=lambda j: [1, 2, 0].index(j))
+
+
+def test_auto_form_picks_precision_only_when_k_exceeds_npi():
+    from paper_1809_09725_amd.serving import pick_form
+    assert pick_form(spec(0, 0.0, K=16), "auto") == "sf"       # Npi = 8
+    assert pick_form(spec(0, 0.0, K=8), "auto") == "pf"
+    assert pick_form(spec(0, 0.0, K=8), "sf") == "sf"
