@@ -161,7 +161,9 @@ int solve(const rt_plan *plan, const rt_solve_params *params, const float *g,
 /* ---- resumable job/step form of solve, for serving ---------------------
  * A job owns the solver state (f~, h1, h2, work arrays) on the device; the
  * caller still owns g and f.  rt_job_create runs the power iteration (if
- * tau/sigma are not given) on `stream` and blocks for its scalars.
+ * tau/sigma are not given) on `stream` and blocks for its scalars; it runs
+ * on slice 0 alone, since R_T applies the same operator to every slice and
+ * its norm is that of the one-slice operator.
  * rt_job_step issues n more iterations on `stream` without blocking (a
  * monitor every check_every iterations blocks for 40 bytes). */
 typedef struct rt_job rt_job;

@@ -469,9 +469,15 @@ double or_seeded_uniform(uint64_t seed, uint64_t j)
 
 /* Largest singular value of R_T by power iteration on R_T* R_T from the
  * seeded start vector: x <- R*R x / |R*R x|, n_pow times, then |R x|. */
-double or_power(const or_geom *g, int route, const double *theta, const double *phi,
+double or_power(const or_geom *gin, int route, const double *theta, const double *phi,
                 int n_pow, uint64_t seed)
 {
+    /* R_T applies the same operator to every slice (parallel beam, Sec. 2),
+     * so it is block-diagonal with identical blocks and its norm is that of
+     * the one-slice operator: the iteration runs on slice 0 alone. */
+    or_geom g1 = *gin;
+    if (g1.Nz > 1) g1.Nz = 1;
+    const or_geom *g = &g1;
     const size_t nf = (size_t)g->Nz * g->N * g->N * g->K;
     const size_t ng = (size_t)g->Ntheta * g->Nz * g->Ns;
     double *x = malloc(sizeof(double) * nf), *y = malloc(sizeof(double) * nf);

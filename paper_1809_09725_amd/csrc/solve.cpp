@@ -65,7 +65,13 @@ int fetch(const Plan &p, int n, double *host, hipStream_t s)
 // L_R = |R_T| by power iteration on R_T* R_T from the seeded start vector.
 int power_iteration(Job &J, hipStream_t s)
 {
-    const Plan &p = *J.plan;
+    // R_T acts on every slice with the same operator (parallel beam), so it
+    // is block-diagonal with identical blocks and ||R_T|| is the norm of the
+    // one-slice operator: iterate on slice 0 only, through a view of the plan
+    // with Nz = 1 (tables and scratch are shared; scratch is sized for Nz >= 1).
+    const Plan &full = *J.plan;
+    Plan p = full;
+    p.g.Nz = full.g.Nz > 0 ? 1 : 0;
     const size_t nf = nf_of(p.g), ng = ng_of(p.g);
     float *x = J.ft, *y = J.work;
     int rc = launch_seeded_uniform(x, nf, J.prm.seed, s);
@@ -81,6 +87,7 @@ int power_iteration(Job &J, hipStream_t s)
     if (!rc) rc = launch_forward(p, x, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
     if (!rc) rc = launch_dot_partials(J.sino, J.sino, ng, p.d_part, nbg, s);
     if (!rc) rc = launch_finish(p.d_part, nbg, 1, p.d_red, s);
+    ++full.shadow_gen;   // the view wrote the plan's BF16 copy of the volume
     double v = 0.0;
     if (!rc) rc = fetch(p, 1, &v, s);
     if (rc) return rc;

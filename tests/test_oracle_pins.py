@@ -342,6 +342,15 @@ def test_power_iteration_matches_svd():
     assert abs(L - smax) <= 1e-10 * smax
 
 
+def test_power_iteration_on_one_slice_is_the_full_norm():
+    # the power iteration runs on slice 0 alone; the dense operator of all
+    # slices (block-diagonal, identical blocks) has the same top singular value
+    g = Geom(N=4, Nz=3, Ns=5, Ntheta=6, Npi=2, K=2, Nt=2)
+    smax = np.linalg.svd(dense_R(g), compute_uv=False)[0]
+    L = O.power(g, n_pow=3000, seed=7)
+    assert abs(L - smax) <= 1e-10 * smax
+
+
 def test_solve_least_squares_limit_is_pinv():
     """lambda1 = 0: h2 is projected to 0, the loop is CP for 1/2|Af-g|^2 from
     f0 = 0, whose iterates stay in range(A^T) and converge to pinv(A) g."""
