@@ -171,6 +171,7 @@ class Scheduler:
         active: list[_Active] = []
         records: dict[int, Record] = {}
         used = 0
+        max_resident = 0
         t0 = be.now()
         while future or waiting or setting_up or active:
             now = be.now() - t0
@@ -196,6 +197,7 @@ class Scheduler:
                 if i == 0 and now - s.arrival >= self.starve_s:
                     break          # reserve freed memory for the oldest job
                 i += 1
+            max_resident = max(max_resident, len(active) + len(setting_up))
             # ---- jobs whose setup finished join the active set
             for a in list(setting_up):
                 if be.ready(a.h):
@@ -230,7 +232,9 @@ class Scheduler:
                 be.wait(nxt)
         makespan = max((r.finished for r in records.values()), default=0.0)
         recs = [records[s.jid] for s in trace]
-        return recs, summarize(recs, makespan)
+        st = summarize(recs, makespan)
+        st["max_resident"] = max_resident
+        return recs, st
 
 
 # --------------------------------------------------------------------------- GPU backend

@@ -42,9 +42,7 @@ def test_served_equals_alone(form):
     recs, st = Scheduler(be, 8 << 30, max_active=4, depth=2, form=form).run(tr)
     be.close()
     assert st["jobs"] == len(tr)
-    # several jobs were resident together (the mix really overlapped)
-    spans = [(r.ready, r.finished) for r in recs]
-    assert any(a[0] < b[1] and b[0] < a[1] for i, a in enumerate(spans) for b in spans[i + 1:])
+    assert st["max_resident"] >= 2      # jobs were resident (and stepped) together
     for s, r in zip(tr, recs):
         assert r.iters == s.n_iter
         ref = alone(s, pick_form(s, form))

@@ -43,6 +43,7 @@ def test_all_jobs_complete_and_accounting():
     assert be.live_bytes == 0
     assert st["makespan_s"] == pytest.approx(max(r.finished for r in recs))
     assert st["p50_latency_s"] <= st["p99_latency_s"]
+    assert 2 <= st["max_resident"] <= 4
     # every issued iteration ran exactly once
     assert sorted(be.order) == sorted(j for s in tr for j in [s.jid] * s.n_iter)
 
