@@ -146,14 +146,11 @@ int check_plan(const rt_plan *p);
 
 // ---------------------------------------------------------------- launchers
 // Projector (proj_pf.hip).  mode of the contraction epilogue:
-// CONTRACT_PROX_FOLD: the h1 prox, and the fold-sum g~ of the new h1 into the
-// plan scratch, when forward_folds(p) (otherwise the same as CONTRACT_PROX).
-enum ContractMode { CONTRACT_STORE = 0, CONTRACT_PROX = 1, CONTRACT_PROX_FOLD = 2 };
+enum ContractMode { CONTRACT_STORE = 0, CONTRACT_PROX = 1 };
 int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const float *gdata,
                       float *h1, float sigma, double *part, hipStream_t s);
 int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s);
 int forward_partials(const Plan &p);      // workgroups (= FP64 partials) of the h1 prox
-bool forward_folds(const Plan &p);        // the h1-prox forward can also write g~
 int launch_backproject(const Plan &p, float *out, hipStream_t s);   // from g~ in d_scr
 // Precision form (proj_sf.hip)
 int launch_forward_sf(const Plan &p, const float *f, float *g, int mode, const float *gdata,

@@ -96,7 +96,6 @@ struct FwdEpi {
     float *out;           // g (EPI_G) or h1 (EPI_PROX)
     const float *gdata;   // measured sinogram (EPI_PROX)
     double *part;         // per-workgroup FP64 sum of (R f~ - g)^2, or NULL
-    float *gt;            // EPI_PROX: also the fold-sum g~ of the new h1, or NULL
     float sigma;
     int mode, n0, Npi;
 };
@@ -221,11 +220,6 @@ __global__ __launch_bounds__(FT) void k_project(
                 if (k0 + k < K) dst[k] = acc[j][k];
             continue;
         }
-        // g~(a,z,b,.) of the new h1: the half-turn values this thread writes
-        // are exactly the terms of the fold-sum for bin b (Sec. 4)
-        float gt[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) gt[k] = 0.f;
         for (int r = 0; r < E.Npi; ++r) {   // every half-turn of class a (K <= KC here)
             const int i = r * E.n0 + a;
             const float *ph = E.phi + (size_t)i * K;
@@ -240,20 +234,8 @@ __global__ __launch_bounds__(FT) void k_project(
             } else {
                 const float d = v - E.gdata[o];
                 d2 += (double)d * (double)d;
-                const float hn = (E.out[o] + E.sigma * d) * inv1s;
-                E.out[o] = hn;
-                if (E.gt) {
-#pragma unroll
-                    for (int k = 0; k < KC; ++k)
-                        if (k < K) gt[k] = fmaf(ph[k], hn, gt[k]);
-                }
+                E.out[o] = (E.out[o] + E.sigma * d) * inv1s;
             }
-        }
-        if (E.gt) {
-            float *dst = E.gt + (((size_t)a * Nz + z) * Ns + b) * K;
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < K) dst[k] = gt[k];
         }
     }
     if (E.part) {
@@ -413,7 +395,6 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     E.out = mode == CONTRACT_STORE ? g : h1;
     E.gdata = gdata;
     E.part = fused ? part : nullptr;
-    E.gt = fused && mode == CONTRACT_PROX_FOLD ? p.d_scr : nullptr;
     E.sigma = sigma;
     E.mode = !fused ? EPI_P : (mode == CONTRACT_STORE ? EPI_G : EPI_PROX);
     E.n0 = p.n0;
@@ -443,8 +424,6 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
-
-bool forward_folds(const Plan &p) { return p.form == RT_FORM_PF && p.fwd.nkc == 1; }
 
 int forward_partials(const Plan &p)
 {

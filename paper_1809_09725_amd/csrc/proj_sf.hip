@@ -380,7 +380,7 @@ int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, f
     E.gdata = gdata;
     E.part = part;
     E.sigma = sigma;
-    E.prox = mode != CONTRACT_STORE;
+    E.prox = mode == CONTRACT_PROX;
     E.n0 = p.n0;
     E.Npi = G.Npi;
     const unsigned nb = sf_blocks(p);

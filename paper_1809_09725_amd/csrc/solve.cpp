@@ -196,7 +196,6 @@ int step_job(Job &J, int n, hipStream_t s)
     const float tau = (float)J.tau, sigma = (float)J.sigma;
     const float l1 = (float)P.lambda1, l2 = (float)P.lambda2;
     int rc = RT_OK;
-    const bool fold = forward_folds(p);
     for (int it = 0; it < n && J.iters < P.n_iter && !J.stopped; ++it) {
         const bool check = P.check_every > 0 && (J.iters + 1) % P.check_every == 0;
         double *pf = check ? p.d_part : nullptr;
@@ -210,16 +209,13 @@ int step_job(Job &J, int n, hipStream_t s)
                 J.shadow_gen = p.shadow_gen;
             }
             if ((rc = launch_forward_sf16(p, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) return rc;
-        } else if ((rc = launch_forward(p, J.ft, nullptr, fold ? CONTRACT_PROX_FOLD : CONTRACT_PROX,
-                                        J.g, J.h1, sigma, pf, s))) {
+        } else if ((rc = launch_forward(p, J.ft, nullptr, CONTRACT_PROX, J.g, J.h1, sigma, pf, s))) {
             return rc;
         }
         // step 4: h2 <- shrink(h2 + sigma grad S f~)
         if ((rc = launch_grad_shrink(p, J.Ff, J.h2, sigma, l1, l2, pg, s))) return rc;
         // steps 5-6: f+ = f - tau R_T* h1 + tau S^T div h2, f~ = 2 f+ - f
-        // R_T* h1: the forward already left the fold-sum of h1 in the scratch
-        if ((rc = fold ? launch_backproject(p, J.work, s) : launch_adjoint(p, J.h1, J.work, s)))
-            return rc;
+        if ((rc = launch_adjoint(p, J.h1, J.work, s))) return rc;
         if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s))) return rc;
         J.shadow_gen = p.shadow_gen;
         ++J.iters;
