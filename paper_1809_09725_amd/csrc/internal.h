@@ -56,6 +56,8 @@ struct FwdCfg {
     int BT = 1;           // bins per tile
     int nbt = 1;          // bin tiles
     int stride = 4;       // floats per staged position (KC + padding)
+    int nbuf = 2;         // LDS line buffers (1 when two padded lines do not fit)
+    bool tl = false;      // two-level ray sums (N > 512)
     int vec = 1;          // 4: float4 staging loads
     int pf = 4;           // float4 per thread that hold one staged line (4 or 8)
     size_t lds = 0;       // bytes of LDS per workgroup
@@ -75,6 +77,7 @@ struct AdjCfg {
 // f has KP = K rounded up to 16 channels per voxel.
 struct SfCfg {
     int A = 1, ngroups = 0, BT = 1, nbt = 1, PCH = 32, CS = 20, NPP = 4, KP = 16;
+    int UB = 1;           // bins per thread and class slot (BT = 512 UB covers Ns <= 2048)
     size_t lds = 0;
 };
 
@@ -160,7 +163,7 @@ int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, f
 int launch_to_bf16(const Plan &p, const float *f, hipStream_t s);            // f -> d_f16
 int launch_fold_mfma(const Plan &p, const float *g, hipStream_t s);
 unsigned sf_blocks(const Plan &p);
-int sf_slots(int npp);   // classes per workgroup the kernel is built for
+int sf_slots(int npp, int ub, int kb);   // classes per workgroup the kernel is built for
 // Dispatch on the plan's form: R_T (with the h1 prox when mode = CONTRACT_PROX) and R_T*
 int launch_forward(const Plan &p, const float *f, float *g, int mode, const float *gdata,
                    float *h1, float sigma, double *part, hipStream_t s);

@@ -114,7 +114,13 @@ static int configure(Plan &p)
     for (int a = 0; a < n0; ++a)
         (std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? rows : cols).push_back(a);
     FwdCfg &F = p.fwd;
-    const int pairs_max = 512 * 4;   // 512 threads x 4 rays
+    // 512 threads x 4 rays; for 512 < N <= 1024, 8 rays of 8-channel chunks:
+    // each workgroup streams its whole slice through, so the re-read traffic
+    // per channel-sample is 2N / (rays per workgroup).  (Register budget of
+    // the two-level ray sums: 16 channels only for N <= 512, 8 rays only with
+    // 8 channels and one line of prefetch in 4 float4.)
+    const bool wide = g.N > 512 && g.N <= 1024 && g.K % 4 == 0;
+    const int pairs_max = 512 * (wide ? 8 : 4);
     F.BT = std::min(g.Ns, pairs_max);
     F.nbt = (g.Ns + F.BT - 1) / F.BT;
     F.A = std::max(1, pairs_max / F.BT);
@@ -129,22 +135,29 @@ static int configure(Plan &p)
         }
     }
     F.ngroups = (int)gwalk.size();
-    // two LDS line buffers; one line must fit the 512 threads' prefetch registers
+    // LDS line buffers with an odd number of 16-byte groups per position
+    // (KC = 4: 4 floats, 8: 12, 16: 20), so that 16 consecutive positions
+    // fall in distinct bank groups: two buffers when they fit, else one; one
+    // line must also fit the 512 threads' prefetch registers (N * KC <= 16384)
     F.KC = 0;
     const int K4 = (g.K + 3) / 4 * 4;
     for (int kc : {16, 8, 4}) {
-        if (F.KC || (kc > K4 && kc != 4) || g.N * kc > 4 * 8 * 512) continue;
-        for (int pad : {4, 0})
-            if (!F.KC && 2 * (size_t)(g.N + 2) * (kc + pad) * sizeof(float) <= 160 * 1024) {
+        const int pfmax = g.K % 4 == 0 && !wide ? 8 : 4;   // float4 of line prefetch per thread
+        const int kcmax = g.K % 4 == 0 && g.N <= 512 ? 16 : 8;
+        if (F.KC || (kc > K4 && kc != 4) || g.N * kc > 4 * pfmax * 512 || kc > kcmax) continue;
+        const int stride = (kc / 4) % 2 ? kc : kc + 4;
+        for (int nbuf : {2, 1})
+            if (!F.KC && nbuf * (size_t)(g.N + 2) * stride * sizeof(float) <= 160 * 1024) {
                 F.KC = kc;
-                F.stride = kc + pad;
+                F.stride = stride;
+                F.nbuf = nbuf;
             }
     }
-    if (!F.KC) return fail(RT_E_SHAPE, "N=%d too large for the projector's staging buffer", g.N);
     F.pf = g.N * F.KC <= 4 * 4 * 512 ? 4 : 8;
+    F.tl = g.N > 512;
     F.nkc = (g.K + F.KC - 1) / F.KC;
     F.vec = (g.K % 4 == 0) ? 4 : 1;
-    F.lds = 2 * (size_t)(g.N + 2) * F.stride * sizeof(float);
+    F.lds = (size_t)F.nbuf * (g.N + 2) * F.stride * sizeof(float);
 
     // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
     AdjCfg &B = p.adj;
@@ -178,7 +191,12 @@ static int configure(Plan &p)
     if (p.form == RT_FORM_SF) {
         SfCfg &C = p.sf;
         C.NPP = (g.Npi + 3) / 4 * 4;
-        C.A = std::min(sf_slots(C.NPP), (int)std::max(rows.size(), cols.size()));
+        // one workgroup covers all bins up to 2048 (each thread up to 4 bins
+        // per class), so that every line's frames are synthesised once
+        C.UB = g.Ns <= 512 ? 1 : g.Ns <= 1024 ? 2 : 4;
+        const int kb = (g.K + 15) / 16;
+        while (C.UB > 1 && C.UB * sf_slots(C.NPP, C.UB, kb) * C.NPP > 64) C.UB /= 2;   // registers
+        C.A = std::min(sf_slots(C.NPP, C.UB, kb), (int)std::max(rows.size(), cols.size()));
         for (int w = 0; w < 2; ++w) {
             const std::vector<int> &L = w == 0 ? rows : cols;
             for (size_t i = 0; i < L.size(); i += C.A) {
@@ -187,7 +205,7 @@ static int configure(Plan &p)
             }
         }
         C.ngroups = (int)gwalk_sf.size();
-        C.BT = std::min(g.Ns, 512);
+        C.BT = std::min(g.Ns, 512 * C.UB);
         C.nbt = (g.Ns + C.BT - 1) / C.BT;
         C.PCH = std::min(512, (g.N + 31) / 32 * 32);
         C.KP = (g.K + 15) / 16 * 16;

@@ -30,7 +30,7 @@ constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
 // Staging of one line (row or column of a slice, KC channels, positions
 // 0..N-1 into LDS slots 1..N) through registers: the loads of line l+1 are
 // issued before the taps of line l are summed, and written to the other LDS
-// buffer afterwards.  PF float4 per thread cover a whole line
+// buffer afterwards (or, with one buffer, over line l once its taps are done).  PF float4 per thread cover a whole line
 // (N * KC <= 4 * PF * FT).  VEC = 4: float4 loads (K % 4 == 0); VEC = 1:
 // scalar loads of the same PF*4 values.
 template <int KC, int PF, int VEC>
@@ -104,14 +104,14 @@ struct FwdEpi {
 // (class, bin) of one group; P(a,z,b,k0..k0+KC) = sum over lines of the
 // linear interpolation between the two positions around the ray, times the
 // line spacing along the ray 1/c.
-template <int KC, int PPT, int PF, int VEC>
+template <int KC, int PPT, int PF, int VEC, bool TL>
 __global__ __launch_bounds__(FT) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
-    int nbt, int nkc, int stride, unsigned nblocks, FwdEpi E)
+    int nbt, int nkc, int stride, int nbuf, unsigned nblocks, FwdEpi E)
 {
-    extern __shared__ float lines[];   // 2 buffers x [N + 2 slots][stride], slots = positions -1 .. N
+    extern __shared__ float lines[];   // nbuf buffers x [N + 2 slots][stride], slots = positions -1 .. N
     __shared__ double sh[FT / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
@@ -151,13 +151,22 @@ __global__ __launch_bounds__(FT) void k_project(
         }
     }
 
-    float acc[PPT][KC];
+    // TL (two-level sums, planned for N > 512): the taps of LB consecutive
+    // lines go into blk, which is added into acc every LB lines, so that the
+    // FP32 rounding of a long ray grows with sqrt(LB) + sqrt(N / LB)
+    // additions instead of sqrt(N)
+    constexpr int LB = 32;
+    float acc[PPT][KC], blk[TL ? PPT : 1][KC];
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
 #pragma unroll
         for (int k = 0; k < KC; ++k) acc[j][k] = 0.f;
+#pragma unroll
+    for (int j = 0; j < (TL ? PPT : 1); ++j)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) blk[j][k] = 0.f;
 
-    for (int e = tid; e < 4 * stride; e += FT) {   // zero slots -1 and N of both buffers
+    for (int e = tid; e < 2 * nbuf * stride; e += FT) {   // zero slots -1 and N of each buffer
         const int b = e / (2 * stride), w = e % (2 * stride);
         lines[b * bufsz + (w < stride ? 0 : (N + 1) * stride) + w % stride] = 0.f;
     }
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(FT) void k_project(
     for (int l = 0; l < N; ++l) {
         const bool more = l + 1 < N;
         if (more) pf.load(f + zoff + (size_t)(l + 1) * lstep, pstep, N, k0, K);
-        const float *line = lines + (l & 1) * bufsz;
+        const float *line = lines + (nbuf == 2 ? (l & 1) * bufsz : 0);
         const double lc = (double)l - hN;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -186,21 +195,40 @@ __global__ __launch_bounds__(FT) void k_project(
             const float w1 = in ? fr * invc[j] : 0.f;
             const float w0 = in ? (1.f - fr) * invc[j] : 0.f;
             const float *t0 = line + (in ? q0 + 1 : 0) * stride;
-#pragma unroll
-            for (int k = 0; k < KC; k += 4) {
-                const float4 x0 = *(const float4 *)(t0 + k);
-                const float4 x1 = *(const float4 *)(t0 + stride + k);
-                acc[j][k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, acc[j][k + 0]));
-                acc[j][k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, acc[j][k + 1]));
-                acc[j][k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, acc[j][k + 2]));
-                acc[j][k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, acc[j][k + 3]));
-            }
-            // finish this ray's FMAs before the next ray's tap loads are issued:
+            // the taps of this ray into s (the ray's sums or its block sums);
+            // its FMAs finish before the next ray's tap loads are issued:
             // hoisting the loads of all rays needs 32 VGPRs per ray and spills
+            auto taps = [&](float (&sr)[KC]) {
 #pragma unroll
-            for (int k = 0; k < KC; ++k) asm volatile("" : "+v"(acc[j][k])::"memory");
+                for (int k = 0; k < KC; k += 4) {
+                    const float4 x0 = *(const float4 *)(t0 + k);
+                    const float4 x1 = *(const float4 *)(t0 + stride + k);
+                    sr[k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, sr[k + 0]));
+                    sr[k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, sr[k + 1]));
+                    sr[k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, sr[k + 2]));
+                    sr[k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, sr[k + 3]));
+                }
+#pragma unroll
+                for (int k = 0; k < KC; ++k) asm volatile("" : "+v"(sr[k])::"memory");
+            };
+            if constexpr (TL) taps(blk[TL ? j : 0]);
+            else taps(acc[j]);
         }
-        if (more) pf.store(lines + ((l + 1) & 1) * bufsz, N, stride);
+        if constexpr (TL) {
+            if ((l + 1) % LB == 0 || !more) {
+#pragma unroll
+                for (int j = 0; j < PPT; ++j)
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) {
+                        acc[j][k] += blk[TL ? j : 0][k];
+                        blk[TL ? j : 0][k] = 0.f;
+                    }
+            }
+        }
+        // line l+1 goes to the other buffer while l is read; with one buffer,
+        // after every thread's taps of line l
+        if (nbuf == 1) __syncthreads();
+        if (more) pf.store(lines + (nbuf == 2 ? ((l + 1) & 1) * bufsz : 0), N, stride);
         __syncthreads();
     }
 
@@ -333,22 +361,38 @@ __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
     }
 }
 
-template <int KC, int PPT, int PF, int VEC>
+template <int KC, int PPT, int PF, int VEC, bool TL>
 static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
                             unsigned nb)
 {
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
-    auto kern = k_project<KC, PPT, PF, VEC>;
+    auto kern = k_project<KC, PPT, PF, VEC, TL>;
     if (F.lds > 64 * 1024)   // beyond the default dynamic LDS limit: ask for what this plan needs
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)F.lds));
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(FT), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
                        p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
-                       F.nkc, F.stride, nb, E);
+                       F.nkc, F.stride, F.nbuf, nb, E);
     kt.stop();
     return RT_OK;
+}
+
+// two-level sums are planned for N > 512, where 16-channel chunks are not
+// used and 8 rays per thread or 8 float4 of prefetch only occur
+template <int KC, int PPT, int PF, int VEC>
+static int launch_project_l(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
+                            unsigned nb)
+{
+    if constexpr (KC == 16) {
+        return launch_project_t<KC, PPT, PF, VEC, false>(p, f, E, s, nb);
+    } else if constexpr (PPT == 8 || PF == 8) {
+        return launch_project_t<KC, PPT, PF, VEC, true>(p, f, E, s, nb);
+    } else {
+        return p.fwd.tl ? launch_project_t<KC, PPT, PF, VEC, true>(p, f, E, s, nb)
+                        : launch_project_t<KC, PPT, PF, VEC, false>(p, f, E, s, nb);
+    }
 }
 
 template <int KC, int PF, int VEC>
@@ -356,9 +400,15 @@ static int launch_project_p(const Plan &p, const float *f, const FwdEpi &E, hipS
                             unsigned nb, int ppt)
 {
     switch (ppt) {
-    case 1: return launch_project_t<KC, 1, PF, VEC>(p, f, E, s, nb);
-    case 2: return launch_project_t<KC, 2, PF, VEC>(p, f, E, s, nb);
-    default: return launch_project_t<KC, 4, PF, VEC>(p, f, E, s, nb);
+    case 1: return launch_project_l<KC, 1, PF, VEC>(p, f, E, s, nb);
+    case 2: return launch_project_l<KC, 2, PF, VEC>(p, f, E, s, nb);
+    case 4: return launch_project_l<KC, 4, PF, VEC>(p, f, E, s, nb);
+    default:   // 8 rays per thread: planned only for KC <= 8 with float4 staging
+        if constexpr (KC <= 8 && VEC == 4 && PF == 4) {
+            return launch_project_l<KC, 8, PF, VEC>(p, f, E, s, nb);
+        } else {
+            return fail(RT_E_SHAPE, "no projection kernel for 8 rays per thread at KC=%d", KC);
+        }
     }
 }
 
@@ -366,8 +416,14 @@ template <int KC, int VEC>
 static int launch_project_k(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
                             unsigned nb, int ppt)
 {
-    return p.fwd.pf <= 4 ? launch_project_p<KC, 4, VEC>(p, f, E, s, nb, ppt)
-                         : launch_project_p<KC, 8, VEC>(p, f, E, s, nb, ppt);
+    // scalar staging (K % 4 != 0) and 16-channel chunks are planned with 4
+    // float4 of prefetch per thread (registers of the two-level ray sums)
+    if constexpr (VEC == 1 || KC == 16) {
+        return launch_project_p<KC, 4, VEC>(p, f, E, s, nb, ppt);
+    } else {
+        return p.fwd.pf <= 4 ? launch_project_p<KC, 4, VEC>(p, f, E, s, nb, ppt)
+                             : launch_project_p<KC, 8, VEC>(p, f, E, s, nb, ppt);
+    }
 }
 
 static unsigned row_blocks(long rows) { return (unsigned)std::min<long>(rows, 4096); }
@@ -387,7 +443,7 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     const FwdCfg &F = p.fwd;
     if (G.Nz == 0) return RT_OK;
     const int pairs = F.A * F.BT;
-    const int ppt = pairs <= FT ? 1 : pairs <= 2 * FT ? 2 : 4;
+    const int ppt = pairs <= FT ? 1 : pairs <= 2 * FT ? 2 : pairs <= 4 * FT ? 4 : 8;
     const unsigned nb = project_blocks(p);
     const bool fused = F.nkc == 1;   // all K channels in one workgroup: contract in the epilogue
     FwdEpi E{};
@@ -407,10 +463,10 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
         default: rc = launch_project_k<16, 4>(p, f, E, s, nb, ppt); break;
         }
     } else {
-        switch (F.KC) {
+        switch (F.KC) {   // the plan keeps KC <= 8 with scalar staging
         case 4: rc = launch_project_k<4, 1>(p, f, E, s, nb, ppt); break;
         case 8: rc = launch_project_k<8, 1>(p, f, E, s, nb, ppt); break;
-        default: rc = launch_project_k<16, 1>(p, f, E, s, nb, ppt); break;
+        default: return fail(RT_E_SHAPE, "no scalar-staging projection for KC=%d", F.KC);
         }
     }
     if (rc) return rc;

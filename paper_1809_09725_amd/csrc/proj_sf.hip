@@ -56,7 +56,7 @@ struct SfEpi {
 // shadow of f.  They land in LDS position-major, row 1 + pos - c0 holding the
 // A*NPP frames of position pos, so that a ray's tap at one position is NPP/4
 // 16-byte reads, the access of the plain form's staged lines.
-template <int NPP, int KB, int AS>
+template <int NPP, int KB, int AS, int UB>
 __global__ __launch_bounds__(ST) void k_project_sf(
     const __bf16 *__restrict__ f16, const float *__restrict__ phi, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
@@ -64,6 +64,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     int nbt, int PCH, int CS, unsigned nblocks, SfEpi E)
 {
     constexpr int KP = 16 * KB;
+    constexpr int R = AS * UB;      // rays per thread: slot rho / UB, bin tid + ST * (rho % UB)
     extern __shared__ float fr[];   // [PCH + 2][CS]; rows 0 and PCH + 1 stay zero
     __shared__ double sh[ST / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
@@ -78,33 +79,33 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
 
     // ---- rays of this thread
-    const int b = bt * BT + tid;
-    double base[AS], slope[AS];
-    float invc[AS];
+    double base[R], slope[R];
+    float invc[R];
 #pragma unroll
-    for (int j = 0; j < AS; ++j) {
+    for (int rho = 0; rho < R; ++rho) {
+        const int j = rho / UB, bi = tid + ST * (rho % UB), b = bt * BT + bi;
         const int a = j < A ? gcls[grp * A + j] : -1;
-        base[j] = -1.0e9;   // far outside: never tapped
-        slope[j] = 0.0;
-        invc[j] = 0.f;
-        if (a >= 0 && tid < BT && b < Ns) {
+        base[rho] = -1.0e9;   // far outside: never tapped
+        slope[rho] = 0.0;
+        invc[rho] = 0.f;
+        if (a >= 0 && bi < BT && b < Ns) {
             const double cs = ccos[a], sn = csin[a], sb = (double)b - hS;
             if (walk == 0) {
-                base[j] = sb / cs + hN;
-                slope[j] = -sn / cs;
-                invc[j] = (float)(1.0 / fabs(cs));
+                base[rho] = sb / cs + hN;
+                slope[rho] = -sn / cs;
+                invc[rho] = (float)(1.0 / fabs(cs));
             } else {
-                base[j] = sb / sn + hN;
-                slope[j] = -cs / sn;
-                invc[j] = (float)(1.0 / fabs(sn));
+                base[rho] = sb / sn + hN;
+                slope[rho] = -cs / sn;
+                invc[rho] = (float)(1.0 / fabs(sn));
             }
         }
     }
-    float acc[AS][NPP];
+    float acc[R][NPP];
 #pragma unroll
-    for (int j = 0; j < AS; ++j)
+    for (int rho = 0; rho < R; ++rho)
 #pragma unroll
-        for (int r = 0; r < NPP; ++r) acc[j][r] = 0.f;
+        for (int r = 0; r < NPP; ++r) acc[rho][r] = 0.f;
 
     // ---- MFMA A operand: Phi[i(c)][k] of frame column c = lane % 32 (slot
     // c / NPP, half-turn c % NPP), channels kb*16 + 8*(lane/32) + 0..7
@@ -150,22 +151,22 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     };
     load_step(0);
 
-    int q0[AS];
-    float w0[AS], w1[AS];
+    int q0[R];
+    float w0[R], w1[R];
     for (int st = 0; st < nsteps; ++st) {
         const int l = st / nch, c0 = (st % nch) * PCH;
         if (c0 == 0) {   // ray positions on line l
             const double lc = (double)l - hN;
 #pragma unroll
-            for (int j = 0; j < AS; ++j) {
-                const double u = fma(lc, slope[j], base[j]);
+            for (int rho = 0; rho < R; ++rho) {
+                const double u = fma(lc, slope[rho], base[rho]);
                 const double fl = floor(u);
                 const int q = (int)fl;
                 const float frc = (float)(u - fl);
                 const bool in = (unsigned)(q + 1) <= (unsigned)N;
-                q0[j] = in ? q : -(1 << 28);
-                w1[j] = in ? frc * invc[j] : 0.f;
-                w0[j] = in ? (1.f - frc) * invc[j] : 0.f;
+                q0[rho] = in ? q : -(1 << 28);
+                w1[rho] = in ? frc * invc[rho] : 0.f;
+                w0[rho] = in ? (1.f - frc) * invc[rho] : 0.f;
             }
         }
         v8bf bop[2][KB];
@@ -198,21 +199,21 @@ __global__ __launch_bounds__(ST) void k_project_sf(
         __syncthreads();
         // taps of the rays whose positions fall in this chunk
 #pragma unroll
-        for (int j = 0; j < AS; ++j) {
-            const int q = q0[j] - c0;
+        for (int rho = 0; rho < R; ++rho) {
+            const int q = q0[rho] - c0;
             const bool t0 = q >= 0 && q < PCH;
             const bool t1 = q >= -1 && q < PCH - 1;
             if (!(t0 || t1)) continue;
-            const float a0 = t0 ? w0[j] : 0.f, a1 = t1 ? w1[j] : 0.f;
-            const float *F0 = fr + (q + 1) * CS + j * NPP;
+            const float a0 = t0 ? w0[rho] : 0.f, a1 = t1 ? w1[rho] : 0.f;
+            const float *F0 = fr + (q + 1) * CS + (rho / UB) * NPP;
 #pragma unroll
             for (int m = 0; m < NPP / 4; ++m) {
                 const float4 x0 = *(const float4 *)(F0 + 4 * m);
                 const float4 x1 = *(const float4 *)(F0 + CS + 4 * m);
-                acc[j][4 * m + 0] = fmaf(a1, x1.x, fmaf(a0, x0.x, acc[j][4 * m + 0]));
-                acc[j][4 * m + 1] = fmaf(a1, x1.y, fmaf(a0, x0.y, acc[j][4 * m + 1]));
-                acc[j][4 * m + 2] = fmaf(a1, x1.z, fmaf(a0, x0.z, acc[j][4 * m + 2]));
-                acc[j][4 * m + 3] = fmaf(a1, x1.w, fmaf(a0, x0.w, acc[j][4 * m + 3]));
+                acc[rho][4 * m + 0] = fmaf(a1, x1.x, fmaf(a0, x0.x, acc[rho][4 * m + 0]));
+                acc[rho][4 * m + 1] = fmaf(a1, x1.y, fmaf(a0, x0.y, acc[rho][4 * m + 1]));
+                acc[rho][4 * m + 2] = fmaf(a1, x1.z, fmaf(a0, x0.z, acc[rho][4 * m + 2]));
+                acc[rho][4 * m + 3] = fmaf(a1, x1.w, fmaf(a0, x0.w, acc[rho][4 * m + 3]));
             }
         }
     }
@@ -221,16 +222,17 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     double d2 = 0.0;
     const float inv1s = 1.f / (1.f + E.sigma);
 #pragma unroll
-    for (int j = 0; j < AS; ++j) {
+    for (int rho = 0; rho < R; ++rho) {
+        const int j = rho / UB, bi = tid + ST * (rho % UB), b = bt * BT + bi;
         const int a = j < A ? gcls[grp * A + j] : -1;
-        if (a < 0 || tid >= BT || b >= Ns) continue;
+        if (a < 0 || bi >= BT || b >= Ns) continue;
 #pragma unroll
         for (int r = 0; r < NPP; ++r) {
             if (r >= Npi) continue;
             const int i = r * E.n0 + a;
             const int bo = (r & 1) ? Ns - 1 - b : b;
             const size_t o = ((size_t)i * Nz + z) * Ns + bo;
-            const float v = acc[j][r];
+            const float v = acc[rho][r];
             if (!E.prox) {
                 E.out[o] = v;
             } else {
@@ -320,12 +322,12 @@ __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
     }
 }
 
-template <int NPP, int KB, int AS>
+template <int NPP, int KB, int AS, int UB>
 static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
 {
     const rt_geom &G = p.g;
     const SfCfg &C = p.sf;
-    auto kern = k_project_sf<NPP, KB, AS>;
+    auto kern = k_project_sf<NPP, KB, AS, UB>;
     if (C.lds > 64 * 1024)
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)C.lds));
@@ -337,14 +339,40 @@ static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
     return RT_OK;
 }
 
+// AS slots for one bin per thread; UB bins per thread take AS / UB slots
+// the slot count sf_slots gives: at most 64 ray sums and 8 rays (4 when
+// K > 48) per thread
+constexpr int fit_slots(int as, int ub, int npp, int kb)
+{
+    return (as > 1 && (as * ub * npp > 64 || as * ub > (kb >= 4 ? 4 : 8)))
+               ? fit_slots(as - 1, ub, npp, kb) : as;
+}
+
+template <int NPP, int KB, int AS>
+static int launch_sf_u(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
+{
+    constexpr int AS2 = fit_slots(AS, 2, NPP, KB), AS4 = fit_slots(AS, 4, NPP, KB);
+    switch (p.sf.UB) {
+    case 1: return launch_sf_t<NPP, KB, fit_slots(AS, 1, NPP, KB), 1>(p, E, s, nb);
+    case 2: return launch_sf_t<NPP, KB, AS2, 2>(p, E, s, nb);
+    default:
+        // the plan keeps UB * slots * NPP <= 64 accumulators per thread
+        if constexpr (4 * AS4 * NPP <= 64) {
+            return launch_sf_t<NPP, KB, AS4, 4>(p, E, s, nb);
+        } else {
+            return fail(RT_E_SHAPE, "no synthesise-first kernel for NPP=%d with 4 bins per thread", NPP);
+        }
+    }
+}
+
 template <int NPP, int AS>
 static int launch_sf_k(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
 {
     switch (p.sf.KP / 16) {
-    case 1: return launch_sf_t<NPP, 1, AS>(p, E, s, nb);
-    case 2: return launch_sf_t<NPP, 2, AS>(p, E, s, nb);
-    case 3: return launch_sf_t<NPP, 3, AS>(p, E, s, nb);
-    default: return launch_sf_t<NPP, 4, AS>(p, E, s, nb);
+    case 1: return launch_sf_u<NPP, 1, AS>(p, E, s, nb);
+    case 2: return launch_sf_u<NPP, 2, AS>(p, E, s, nb);
+    case 3: return launch_sf_u<NPP, 3, AS>(p, E, s, nb);
+    default: return launch_sf_u<NPP, 4, AS>(p, E, s, nb);
     }
 }
 
@@ -352,7 +380,12 @@ static int launch_sf_k(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
 
 unsigned sf_blocks(const Plan &p) { return (unsigned)p.g.Nz * p.sf.ngroups * p.sf.nbt; }
 
-int sf_slots(int npp) { return npp <= 8 ? 4 : npp <= 16 ? 2 : 1; }
+int sf_slots(int npp, int ub, int kb)
+{
+    int as = npp <= 8 ? 4 : npp <= 16 ? 2 : 1;
+    while (as > 1 && (as * ub * npp > 64 || as * ub > (kb >= 4 ? 4 : 8))) --as;   // registers
+    return as;
+}
 
 int launch_to_bf16(const Plan &p, const float *f, hipStream_t s)
 {

@@ -36,6 +36,9 @@ SHAPES = [
     rt4d.Geom(N=70, Nz=2, Ns=70, Ntheta=4 * 25, Npi=4, K=12, Nt=4),    # two channel chunks
     rt4d.Geom(N=33, Nz=2, Ns=40, Ntheta=2 * 45, Npi=2, K=16, Nt=2),
     rt4d.Geom(N=40, Nz=1, Ns=31, Ntheta=12, Npi=1, K=1, Nt=1),         # static, K = 1
+    rt4d.Geom(N=16, Nz=2, Ns=2100, Ntheta=4 * 4, Npi=4, K=4, Nt=4),    # 2 bin tiles
+    rt4d.Geom(N=1024, Nz=1, Ns=96, Ntheta=2 * 8, Npi=2, K=8, Nt=2),    # 8 rays per thread
+    rt4d.Geom(N=2048, Nz=1, Ns=64, Ntheta=2 * 4, Npi=2, K=16, Nt=2),   # ... and one line buffer
     rt4d.Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1),            # one ray
 ]
 
@@ -242,8 +245,10 @@ SF_SHAPES = [
     C1,
     rt4d.Geom(N=45, Nz=3, Ns=50, Ntheta=3 * 37, Npi=3, K=5, Nt=3),
     rt4d.Geom(N=70, Nz=2, Ns=70, Ntheta=4 * 25, Npi=4, K=12, Nt=4),
-    rt4d.Geom(N=600, Nz=1, Ns=530, Ntheta=12 * 6, Npi=12, K=16, Nt=12),   # 2 chunks, 2 bin tiles
+    rt4d.Geom(N=600, Nz=1, Ns=530, Ntheta=12 * 6, Npi=12, K=16, Nt=12),   # 2 chunks, 2 bins/thread
     rt4d.Geom(N=48, Nz=2, Ns=48, Ntheta=12 * 20, Npi=12, K=32, Nt=6),
+    rt4d.Geom(N=40, Nz=1, Ns=1100, Ntheta=8 * 3, Npi=8, K=8, Nt=8),       # 4 bins per thread
+    rt4d.Geom(N=16, Nz=2, Ns=2100, Ntheta=4 * 4, Npi=4, K=4, Nt=4),       # 2 bin tiles of 2048
     rt4d.Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1),
 ]
 
