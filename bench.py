@@ -48,9 +48,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def c2_geom():
+# Workloads: (N, Nz, Ns, Ntheta, Npi, K, Nt), the form they are quoted in, and
+# the moving-phantom family that makes their data.
+WORKLOADS = {
+    "c2": dict(geom=(512, 128, 512, 1800, 10, 16, 10), form="pf", n_ell=40, drift=0.0,
+               sphere=(10.0, 60.0, 0.5), seed=2,
+               desc="plain FP32 R_T/R_T* + 4D TV Chambolle-Pock iteration, 512x512x128 volume, "
+                    "K=16 cosine basis, 1800 projections over 10 half-turns, 512 bins, 10 TV "
+                    "frames, 40 moving ellipsoids + growing sphere, 1% noise"),
+    "c3": dict(geom=(1024, 64, 1024, 3600, 12, 16, 12), form="sf", n_ell=40, drift=0.0,
+               sphere=(20.0, 120.0, 0.5), seed=3,
+               desc="precision form (BF16 MFMA basis contraction, FP32 projection) iteration, "
+                    "1024x1024x64 volume, K=16, 3600 projections over 12 half-turns, 1024 bins, "
+                    "12 TV frames, 40 moving ellipsoids + growing sphere, 1% noise"),
+    "c5": dict(geom=(2048, 32, 2048, 3600, 12, 32, 12), form="sf", n_ell=200, drift=0.5,
+               sphere=None, seed=5,
+               desc="large slab, precision form iteration, 2048x2048x32 volume, K=32, 3600 "
+                    "projections over 12 half-turns, 2048 bins, 12 TV frames, 200 ellipsoids "
+                    "with linear motion and density drift, 1% noise, all state resident in HBM"),
+}
+
+
+def workload_geom(name: str):
     from paper_1809_09725_amd import rt4d
-    return rt4d.Geom(N=512, Nz=128, Ns=512, Ntheta=1800, Npi=10, K=16, Nt=10)
+    N, Nz, Ns, Nth, Npi, K, Nt = WORKLOADS[name]["geom"]
+    return rt4d.Geom(N=N, Nz=Nz, Ns=Ns, Ntheta=Nth, Npi=Npi, K=K, Nt=Nt)
+
+
+def c2_geom():
+    return workload_geom("c2")
 
 
 def algorithmic(kernel: str, G, sf: bool = False) -> tuple[str, float]:
@@ -82,10 +108,10 @@ def source_sha(kernel: str) -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
+def traffic_from_profiles(kernel: str, workload: str = "c2"):
     """HBM bytes per launch from the committed counter summary, or None when
     there is none or the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -217,9 +243,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
-    ap.add_argument("--form", choices=("pf", "sf"), default="pf",
-                    help="pf: plain FP32 project-first (the workload's form); sf: precision "
-                         "form (BF16 basis contraction on MFMA, FP32 projection)")
+    ap.add_argument("--workload", choices=tuple(WORKLOADS), default="c2",
+                    help="c2: 512^2 x 128 plain FP32 (default); c3: 1024^2 x 64 precision "
+                         "form; c5: 2048^2 x 32 slab, K=32, precision form")
+    ap.add_argument("--form", choices=("pf", "sf"), default=None,
+                    help="pf: plain FP32 project-first; sf: precision form (BF16 basis "
+                         "contraction on MFMA, FP32 projection); default: the workload's form")
     ap.add_argument("--kernels-only", action="store_true",
                     help="uniform random sinogram instead of the phantom (same kernels and "
                          "launch shapes; fewer auxiliary launches, for counter runs)")
@@ -254,18 +283,23 @@ def main() -> int:
     from paper_1809_09725_amd import inputs, rt4d
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    G = c2_geom()
-    log(f"workload {G}")
-    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 40, seed=2, axis_range=(G.N / 64, G.N / 16),
+    W = WORKLOADS[args.workload]
+    if args.form is None:
+        args.form = W["form"]
+    G = workload_geom(args.workload)
+    log(f"workload {args.workload}: {G}, form {args.form}")
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, W["n_ell"], seed=W["seed"],
+                             axis_range=(G.N / 64, G.N / 16),
                              z_axis_range=(G.Nz / 16, G.Nz / 4), rho_range=(0.1, 0.5),
-                             speed_per_halfturn=G.N / 64, sphere=(10.0, 60.0, 0.5))
+                             speed_per_halfturn=G.N / 64, drift=W["drift"], sphere=W["sphere"])
     t0 = time.perf_counter()
     if args.kernels_only:
         gen = torch.Generator(device=dev)
         gen.manual_seed(2)
         g = torch.rand(G.g_shape, generator=gen, device=dev)
     else:
-        g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=2, device="cuda")
+        g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=W["seed"],
+                            device="cuda")
     torch.cuda.synchronize()
     log(f"sinogram synthesised in {time.perf_counter() - t0:.1f} s")
     f = torch.zeros(G.f_shape, device=dev)
@@ -316,7 +350,8 @@ def main() -> int:
     else:
         achieved, peak, unit = work / dur / 1e12, PEAK_FP32_VALU / 1e12, "TFLOP/s"
     roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom),
+            "unit": unit, "frac": round(achieved / peak, 4),
+            "traffic": traffic_from_profiles(dom, args.workload),
             "launch_ms": round(dur * 1e3, 4)}
     kern = {}
     for k, (ms, n) in per.items():
@@ -331,10 +366,7 @@ def main() -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.form == "pf" else "bf16+f32", "data": "synthetic",
-        "config": {"workload": "plain FP32 R_T/R_T* + 4D TV Chambolle-Pock iteration, "
-                               "512x512x128 volume, K=16 cosine basis, 1800 projections over "
-                               "10 half-turns, 512 bins, 10 TV frames, 40 moving ellipsoids + "
-                               "growing sphere, 1% noise",
+        "config": {"workload": W["desc"],
                    "N": G.N, "Nz": G.Nz, "Ns": G.Ns, "Ntheta": G.Ntheta, "Npi": G.Npi, "K": G.K,
                    "Nt": G.Nt, "form": args.form.upper(),
                    "precision": "fp32" if args.form == "pf" else "bf16 contraction + fp32 projection",
@@ -343,8 +375,10 @@ def main() -> int:
         "roofline": roof, "kernels": kern,
     }
     if not args.no_cpu_baseline:
-        log(f"timing the CPU oracle on {CPU_SLICES} slices ...")
-        out["cpu_baseline"] = cpu_baseline(G, g[:, 0:CPU_SLICES, :].cpu().numpy(), 3)
+        # about 15 s of oracle work: 16 slices at 512^2 x 1800 angles, fewer for larger slices
+        nsl = max(1, min(G.Nz, round(CPU_SLICES * (512 / G.N) ** 2 * 1800 / G.Ntheta)))
+        log(f"timing the CPU oracle on {nsl} slices ...")
+        out["cpu_baseline"] = cpu_baseline(G, g[:, 0:nsl, :].cpu().numpy(), 3)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -195,7 +195,8 @@ static int configure(Plan &p)
         // per class), so that every line's frames are synthesised once
         C.UB = g.Ns <= 512 ? 1 : g.Ns <= 1024 ? 2 : 4;
         const int kb = (g.K + 15) / 16;
-        while (C.UB > 1 && C.UB * sf_slots(C.NPP, C.UB, kb) * C.NPP > 64) C.UB /= 2;   // registers
+        while (C.UB > 1 && C.UB * sf_slots(C.NPP, C.UB, kb) * C.NPP > (kb >= 3 ? 64 : 96))
+            C.UB /= 2;   // registers
         C.A = std::min(sf_slots(C.NPP, C.UB, kb), (int)std::max(rows.size(), cols.size()));
         for (int w = 0; w < 2; ++w) {
             const std::vector<int> &L = w == 0 ? rows : cols;

@@ -340,11 +340,12 @@ static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
 }
 
 // AS slots for one bin per thread; UB bins per thread take AS / UB slots
-// the slot count sf_slots gives: at most 64 ray sums and 8 rays (4 when
-// K > 48) per thread
+// the slot count sf_slots gives: at most 96 ray sums and 8 rays per thread
+// (64 and 4 when K > 32)
+constexpr int acc_cap(int kb) { return kb >= 3 ? 64 : 96; }
 constexpr int fit_slots(int as, int ub, int npp, int kb)
 {
-    return (as > 1 && (as * ub * npp > 64 || as * ub > (kb >= 4 ? 4 : 8)))
+    return (as > 1 && (as * ub * npp > acc_cap(kb) || as * ub > (kb >= 3 ? 4 : 8)))
                ? fit_slots(as - 1, ub, npp, kb) : as;
 }
 
@@ -356,8 +357,8 @@ static int launch_sf_u(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
     case 1: return launch_sf_t<NPP, KB, fit_slots(AS, 1, NPP, KB), 1>(p, E, s, nb);
     case 2: return launch_sf_t<NPP, KB, AS2, 2>(p, E, s, nb);
     default:
-        // the plan keeps UB * slots * NPP <= 64 accumulators per thread
-        if constexpr (4 * AS4 * NPP <= 64) {
+        // the plan keeps UB * slots * NPP within acc_cap accumulators per thread
+        if constexpr (4 * AS4 * NPP <= acc_cap(KB)) {
             return launch_sf_t<NPP, KB, AS4, 4>(p, E, s, nb);
         } else {
             return fail(RT_E_SHAPE, "no synthesise-first kernel for NPP=%d with 4 bins per thread", NPP);
@@ -383,7 +384,7 @@ unsigned sf_blocks(const Plan &p) { return (unsigned)p.g.Nz * p.sf.ngroups * p.s
 int sf_slots(int npp, int ub, int kb)
 {
     int as = npp <= 8 ? 4 : npp <= 16 ? 2 : 1;
-    while (as > 1 && (as * ub * npp > 64 || as * ub > (kb >= 4 ? 4 : 8))) --as;   // registers
+    while (as > 1 && (as * ub * npp > (kb >= 3 ? 64 : 96) || as * ub > (kb >= 3 ? 4 : 8))) --as;
     return as;
 }
 

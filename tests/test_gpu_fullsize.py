@@ -100,8 +100,10 @@ def test_c2_precision_sampled_slices():
     check_sampled(C2, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA, (5,), (5,), 3e-3)
 
 
-def test_c3_precision_sampled_slice():
-    check_sampled(C3, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA, (63,), (0,), 3e-3)
+def test_c3_precision_sampled_slices():
+    # the precision form's error against the FP64 oracle on a subset of the 64 slices
+    check_sampled(C3, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA, (0, 9, 18, 27, 36, 45, 54, 63),
+                  (0, 63), 3e-3)
 
 
 def test_c5_properties():
