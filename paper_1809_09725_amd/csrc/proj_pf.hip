@@ -320,42 +320,57 @@ __global__ __launch_bounds__(NT) void k_contract(
 }
 
 // g~(a,z,b,k) = sum_rot Phi[rot*n0+a][k] g(rot*n0+a, z, b')  (fold-sum, Sec. 4).
-// One thread per (bin, group of 4 channels): consecutive threads write
-// consecutive 16-byte pieces of g~.
+// A workgroup takes one class a and a run of ZB slices: the class's Phi rows
+// are staged in LDS once, and each thread owns one bin of one slice: it reads
+// the Npi half-turn values of g once each and writes the bin's K channels
+// (consecutive threads write consecutive rows of g~).
+template <int KB4>   // channels in float4 groups: K <= 4 * KB4
 __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
                                              const float *__restrict__ phi,
                                              float *__restrict__ gt, int Nz, int Ns, int K,
-                                             int n0, int Npi)
+                                             int n0, int Npi, int ZB)
 {
-    extern __shared__ float sphi[];   // Phi rows of the current class: [Npi][K]
-    const int KQ = (K + 3) / 4;
-    const long rows = (long)n0 * Nz;
-    for (long row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int a = (int)(row / Nz), z = (int)(row % Nz);
-        __syncthreads();
-        for (int e = threadIdx.x; e < Npi * K; e += NT)
-            sphi[e] = phi[(size_t)((e / K) * n0 + a) * K + e % K];
-        __syncthreads();
-        float *dst = gt + ((size_t)a * Nz + z) * Ns * K;
-        for (int e = threadIdx.x; e < Ns * KQ; e += NT) {
-            const int b = e / KQ, k0 = 4 * (e % KQ);
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            for (int rot = 0; rot < Npi; ++rot) {
-                const int i = rot * n0 + a;
-                const int bp = (rot & 1) ? Ns - 1 - b : b;
-                const float v = g[((size_t)i * Nz + z) * Ns + bp];
-                const float *ph = sphi + rot * K + k0;
+    extern __shared__ float sphi[];   // Phi rows of class a: [Npi][4 * KB4], zero padded
+    const int nzb = (Nz + ZB - 1) / ZB;
+    const int a = blockIdx.x / nzb, z0 = (blockIdx.x % nzb) * ZB;
+    constexpr int KP = 4 * KB4;
+    for (int e = threadIdx.x; e < Npi * KP; e += NT) {
+        const int r = e / KP, k = e % KP;
+        sphi[e] = k < K ? phi[(size_t)(r * n0 + a) * K + k] : 0.f;
+    }
+    __syncthreads();
+    const int z1 = min(Nz, z0 + ZB);
+    for (int e = threadIdx.x; e < (z1 - z0) * Ns; e += NT) {
+        const int z = z0 + e / Ns, b = e % Ns;
+        float4 acc[KB4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k0 + k < K) acc[k] = fmaf(ph[k], v, acc[k]);
+        for (int q = 0; q < KB4; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int rot = 0; rot < Npi; ++rot) {
+            const int i = rot * n0 + a;
+            const int bp = (rot & 1) ? Ns - 1 - b : b;
+            const float v = g[((size_t)i * Nz + z) * Ns + bp];
+            const float4 *ph = (const float4 *)(sphi + rot * KP);
+#pragma unroll
+            for (int q = 0; q < KB4; ++q) {
+                const float4 w = ph[q];
+                acc[q].x = fmaf(w.x, v, acc[q].x);
+                acc[q].y = fmaf(w.y, v, acc[q].y);
+                acc[q].z = fmaf(w.z, v, acc[q].z);
+                acc[q].w = fmaf(w.w, v, acc[q].w);
             }
-            float *d = dst + (size_t)b * K + k0;
-            if ((K & 3) == 0) {
-                *(float4 *)d = make_float4(acc[0], acc[1], acc[2], acc[3]);
-            } else {
+        }
+        float *d = gt + (((size_t)a * Nz + z) * Ns + b) * K;
+        if ((K & 3) == 0) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k0 + k < K) d[k] = acc[k];
+            for (int q = 0; q < KB4; ++q)
+                if (4 * q < K) *(float4 *)(d + 4 * q) = acc[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < KB4; ++q) {
+                const float c[4] = {acc[q].x, acc[q].y, acc[q].z, acc[q].w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (4 * q + t < K) d[4 * q + t] = c[t];
             }
         }
     }
@@ -507,11 +522,19 @@ int launch_adjoint_pf(const Plan &p, const float *g, float *out, hipStream_t s)
 {
     const rt_geom &G = p.g;
     if (G.Nz == 0) return RT_OK;
-    const unsigned nbf = row_blocks((long)p.n0 * G.Nz);
+    // a workgroup per class and run of ZB slices (about 4 bins per thread)
+    const int ZB = std::max(1, std::min(G.Nz, 4 * NT / std::max(1, G.Ns)));
+    const unsigned nbf = (unsigned)p.n0 * ((G.Nz + ZB - 1) / ZB);
+    const int kb4 = (G.K + 3) / 4;
+    const size_t lds = (size_t)G.Npi * 4 * (kb4 <= 2 ? 2 : kb4 <= 4 ? 4 : kb4 <= 8 ? 8 : 16) * sizeof(float);
     KTimer kt("k_fold", s);
-    hipLaunchKernelGGL(k_fold, dim3(nbf), dim3(NT), (size_t)G.Npi * G.K * sizeof(float), s, g,
-                       p.d_phi, p.d_scr, G.Nz, G.Ns, G.K,
-                       p.n0, G.Npi);
+#define RT_FOLD(B) hipLaunchKernelGGL(k_fold<B>, dim3(nbf), dim3(NT), lds, s, g, p.d_phi, p.d_scr, \
+                                      G.Nz, G.Ns, G.K, p.n0, G.Npi, ZB)
+    if (kb4 <= 2) RT_FOLD(2);
+    else if (kb4 <= 4) RT_FOLD(4);
+    else if (kb4 <= 8) RT_FOLD(8);
+    else RT_FOLD(16);
+#undef RT_FOLD
     kt.stop();
     RT_HIP(hipGetLastError());
     return launch_backproject(p, out, s);
