@@ -60,6 +60,7 @@ struct FwdCfg {
     bool tl = false;      // two-level ray sums (N > 512)
     int vec = 1;          // 4: float4 staging loads
     int pf = 4;           // float4 per thread that hold one staged line (4 or 8)
+    int nth = 512;        // threads per workgroup (1024: 16 waves of 2 rays, KC = 16)
     size_t lds = 0;       // bytes of LDS per workgroup
 };
 

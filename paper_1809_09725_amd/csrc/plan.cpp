@@ -158,6 +158,11 @@ static int configure(Plan &p)
     F.nkc = (g.K + F.KC - 1) / F.KC;
     F.vec = (g.K % 4 == 0) ? 4 : 1;
     F.lds = (size_t)F.nbuf * (g.N + 2) * F.stride * sizeof(float);
+    // 16-channel chunks over more than 1024 rays: 1024 threads of 2 rays each.
+    // The group (and so the slice re-read traffic) is the same as with 512
+    // threads of 4 rays, at half the registers per thread, so twice the
+    // waves share the CU's LDS and VALU.
+    F.nth = F.KC == 16 && F.vec == 4 && !F.tl && F.A * F.BT > 1024 && g.N <= 512 ? 1024 : 512;
 
     // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
     AdjCfg &B = p.adj;

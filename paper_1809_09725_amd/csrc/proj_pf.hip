@@ -33,7 +33,7 @@ constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
 // buffer afterwards (or, with one buffer, over line l once its taps are done).  PF float4 per thread cover a whole line
 // (N * KC <= 4 * PF * FT).  VEC = 4: float4 loads (K % 4 == 0); VEC = 1:
 // scalar loads of the same PF*4 values.
-template <int KC, int PF, int VEC>
+template <int KC, int PF, int VEC, int NTH>
 struct LinePrefetch {
     float4 r[PF];
     __device__ inline void load(const float *__restrict__ src, size_t pstep, int N, int k0, int K)
@@ -42,7 +42,7 @@ struct LinePrefetch {
             constexpr int NQ = KC / 4;
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
-                const int e = threadIdx.x + FT * j;
+                const int e = threadIdx.x + NTH * j;
                 const int pos = e / NQ, kq = e % NQ;
                 r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (pos < N && k0 + 4 * kq < K) r[j] = *(const float4 *)(src + (size_t)pos * pstep + 4 * kq);
@@ -53,7 +53,7 @@ struct LinePrefetch {
                 float v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int e = threadIdx.x + FT * (4 * j + i);
+                    const int e = threadIdx.x + NTH * (4 * j + i);
                     const int pos = e / KC, kk = e % KC;
                     v[i] = (pos < N && k0 + kk < K) ? src[(size_t)pos * pstep + kk] : 0.f;
                 }
@@ -67,7 +67,7 @@ struct LinePrefetch {
             constexpr int NQ = KC / 4;
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
-                const int e = threadIdx.x + FT * j;
+                const int e = threadIdx.x + NTH * j;
                 const int pos = e / NQ, kq = e % NQ;
                 if (pos < N) *(float4 *)(buf + (pos + 1) * stride + 4 * kq) = r[j];
             }
@@ -77,7 +77,7 @@ struct LinePrefetch {
                 const float v[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int e = threadIdx.x + FT * (4 * j + i);
+                    const int e = threadIdx.x + NTH * (4 * j + i);
                     const int pos = e / KC, kk = e % KC;
                     if (pos < N) buf[(pos + 1) * stride + kk] = v[i];
                 }
@@ -104,15 +104,15 @@ struct FwdEpi {
 // (class, bin) of one group; P(a,z,b,k0..k0+KC) = sum over lines of the
 // linear interpolation between the two positions around the ray, times the
 // line spacing along the ray 1/c.
-template <int KC, int PPT, int PF, int VEC, bool TL>
-__global__ __launch_bounds__(FT) void k_project(
+template <int KC, int PPT, int PF, int VEC, bool TL, int NTH>
+__global__ __launch_bounds__(NTH) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
     int nbt, int nkc, int stride, int nbuf, unsigned nblocks, FwdEpi E)
 {
     extern __shared__ float lines[];   // nbuf buffers x [N + 2 slots][stride], slots = positions -1 .. N
-    __shared__ double sh[FT / 64];
+    __shared__ double sh[NTH / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
     lid /= nbt;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(FT) void k_project(
     float invc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int pr = tid + FT * j;
+        const int pr = tid + NTH * j;
         const int slot = pr / BT;
         const int b = bt * BT + pr % BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(FT) void k_project(
 #pragma unroll
         for (int k = 0; k < KC; ++k) blk[j][k] = 0.f;
 
-    for (int e = tid; e < 2 * nbuf * stride; e += FT) {   // zero slots -1 and N of each buffer
+    for (int e = tid; e < 2 * nbuf * stride; e += NTH) {   // zero slots -1 and N of each buffer
         const int b = e / (2 * stride), w = e % (2 * stride);
         lines[b * bufsz + (w < stride ? 0 : (N + 1) * stride) + w % stride] = 0.f;
     }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(FT) void k_project(
     const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;   // next line
     const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;   // next position
 
-    LinePrefetch<KC, PF, VEC> pf;
+    LinePrefetch<KC, PF, VEC, NTH> pf;
     pf.load(f + zoff, pstep, N, k0, K);
     pf.store(lines, N, stride);
     __syncthreads();
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(FT) void k_project(
     const float inv1s = 1.f / (1.f + E.sigma);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int pr = tid + FT * j;
+        const int pr = tid + NTH * j;
         const int slot = pr / BT;
         const int b = bt * BT + pr % BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
@@ -376,18 +376,18 @@ __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
     }
 }
 
-template <int KC, int PPT, int PF, int VEC, bool TL>
+template <int KC, int PPT, int PF, int VEC, bool TL, int NTH = FT>
 static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
                             unsigned nb)
 {
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
-    auto kern = k_project<KC, PPT, PF, VEC, TL>;
+    auto kern = k_project<KC, PPT, PF, VEC, TL, NTH>;
     if (F.lds > 64 * 1024)   // beyond the default dynamic LDS limit: ask for what this plan needs
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)F.lds));
     KTimer kt("k_project", s);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(FT), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(NTH), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
                        p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
                        F.nkc, F.stride, F.nbuf, nb, E);
     kt.stop();
@@ -458,7 +458,8 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     const FwdCfg &F = p.fwd;
     if (G.Nz == 0) return RT_OK;
     const int pairs = F.A * F.BT;
-    const int ppt = pairs <= FT ? 1 : pairs <= 2 * FT ? 2 : pairs <= 4 * FT ? 4 : 8;
+    const int nth = F.nth;
+    const int ppt = pairs <= nth ? 1 : pairs <= 2 * nth ? 2 : pairs <= 4 * nth ? 4 : 8;
     const unsigned nb = project_blocks(p);
     const bool fused = F.nkc == 1;   // all K channels in one workgroup: contract in the epilogue
     FwdEpi E{};
@@ -471,7 +472,13 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
     E.n0 = p.n0;
     E.Npi = G.Npi;
     int rc;
-    if (F.vec == 4) {
+    if (nth == 2 * FT) {
+        // 16 waves of 2 rays: planned only for 16-channel float4 staging of
+        // lines of at most 512 positions (2 float4 of prefetch per thread)
+        if (F.vec != 4 || F.KC != 16 || ppt != 2 || F.tl || G.N * 16 > 4 * 2 * 2 * FT)
+            return fail(RT_E_SHAPE, "no 1024-thread projection kernel for this plan");
+        rc = launch_project_t<16, 2, 2, 4, false, 2 * FT>(p, f, E, s, nb);
+    } else if (F.vec == 4) {
         switch (F.KC) {
         case 4: rc = launch_project_k<4, 4>(p, f, E, s, nb, ppt); break;
         case 8: rc = launch_project_k<8, 4>(p, f, E, s, nb, ppt); break;
