@@ -216,5 +216,44 @@ def solve(g: Geom, data, *, lambda1: float, lambda2: float, n_iter: int, f0=None
     return f, {n: getattr(rep, n) for n, _ in _Report._fields_}
 
 
+def shepp_logan(g: Geom, s) -> np.ndarray:
+    """Projections convolved with the Shepp-Logan kernel over the detector
+    (the filter of the FBP initial guess, Secs. 5-6)."""
+    s = _f64(s).reshape(g.Ntheta, g.Nz, g.Ns)
+    out = np.zeros((g.Ntheta, g.Nz, g.Ns))
+    _L().or_shepp_logan(ctypes.byref(g.c()), _p(s), _p(out))
+    return out
+
+
+def half_turn_means(g: Geom, phi=None) -> np.ndarray:
+    """B[m][k]: the mean of phi_k over the projections of half-turn m.  A
+    frame reconstructed from one half-turn sees the object averaged over
+    that half-turn, sum_k B[m][k] f_k."""
+    phi = tables(g)["phi"] if phi is None else _f64(phi)
+    return phi.reshape(g.Npi, g.n0, g.K).mean(axis=1)
+
+
+def fbp_frames(g: Geom, s) -> np.ndarray:
+    """One static FBP per half-turn (Sec. 5: frame m from the projections in
+    [m pi, (m+1) pi)): the filtered projections of half-turn m, back-projected
+    with the transpose of the projector and weighted by the angle step
+    pi / Ntheta0.  Returns (Nz, N, N, Npi)."""
+    q = shepp_logan(g, s)
+    gm = Geom(g.N, g.Nz, g.Ns, g.Ntheta, g.Npi, g.Npi, g.Npi)
+    rot = tables(g)["rot"]
+    ind = np.zeros((g.Ntheta, g.Npi))
+    ind[np.arange(g.Ntheta), rot] = np.pi / g.n0
+    return adjoint(gm, q, phi=ind)
+
+
+def fbp(g: Geom, s, phi=None) -> np.ndarray:
+    """Initial guess f_k (Secs. 5-6): the half-turn FBP frames F_m, then the
+    minimum-norm least-squares coefficients of sum_k B[m][k] f_k = F_m
+    (numpy's pseudo-inverse of B).  Returns (Nz, N, N, K)."""
+    F = fbp_frames(g, s)
+    A = np.linalg.pinv(half_turn_means(g, phi))      # (K, Npi)
+    return F @ A.T
+
+
 def num_threads() -> int:
     return _L().or_num_threads()

@@ -42,6 +42,8 @@
  *   or_tv_norm           Sec. 2 eq. TV1 (value of the penalty, unweighted)
  *   or_power             power iteration for ||R_T|| (step-size rule)
  *   or_solve             Sec. 3 Fig. 2 (adapted Chambolle-Pock loop)
+ *   or_shepp_logan      Secs. 5-6, the FBP initial guess: projections
+ *                        convolved with the Shepp-Logan kernel
  */
 #include <math.h>
 #include <stdint.h>
@@ -619,6 +621,33 @@ int or_solve(const or_geom *g, const double *theta, const double *phi, const dou
     rep->objective = 0.5 * res2 + prm->lambda1 * or_tv_norm(g, S, prm->lambda2, f);
     free(ft); free(fn); free(h1); free(Rf); free(h2); free(gr); free(adj); free(dv);
     return 0;
+}
+
+/* ------------------------------------------------ FBP initial guess */
+
+/* Secs. 5-6 start the iteration from a filtered back-projection that uses
+ * the Shepp-Logan filter.  For unit bin spacing its kernel is
+ *   h(n) = -2 / (pi^2 (4 n^2 - 1))            (Shepp and Logan, 1974)
+ * and each projection row is convolved with it over the detector, bins
+ * outside [0, Ns) being zero:
+ *   q(i,z,b) = sum_{b'=0}^{Ns-1} h(b - b') g(i,z,b'). */
+void or_shepp_logan(const or_geom *g, const double *gin, double *q)
+{
+    const int Ns = g->Ns;
+    const long rows = (long)g->Ntheta * g->Nz;
+#pragma omp parallel for schedule(static)
+    for (long row = 0; row < rows; ++row) {
+        const double *in = gin + row * Ns;
+        double *out = q + row * Ns;
+        for (int b = 0; b < Ns; ++b) {
+            double v = 0.0;
+            for (int bp = 0; bp < Ns; ++bp) {
+                const double n = (double)(b - bp);
+                v += -2.0 / (M_PI * M_PI * (4.0 * n * n - 1.0)) * in[bp];
+            }
+            out[b] = v;
+        }
+    }
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
