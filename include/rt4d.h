@@ -158,6 +158,26 @@ typedef struct {
 int solve(const rt_plan *plan, const rt_solve_params *params, const float *g,
           float *f, rt_solve_report *report, void *stream);
 
+/* ---- initial guess (Secs. 5-6: the iteration starts from an FBP) ---------
+ * q = the projections convolved over the detector with the Shepp-Logan
+ * kernel h(n) = -2 / (pi^2 (4 n^2 - 1)) (unit bin spacing; bins outside
+ * [0, Ns) count as zero).  Device g, q, both [Ntheta][Nz][Ns]; async on
+ * `stream`. */
+int rt_fbp_filter(const rt_plan *plan, const float *g, float *q, void *stream);
+
+/* f_out = the FBP initial guess in coefficient form.  Frame m (m < Npi) is
+ * the static FBP of half-turn m (Sec. 5): the filtered projections of that
+ * half-turn, back-projected with the transpose of the projector and weighted
+ * by pi / Ntheta0.  A frame sees the object averaged over its half-turn, so
+ * f_out holds the minimum-norm least-squares coefficients of
+ *   sum_k B[m][k] f_k = F_m,  B[m][k] = mean of Phi[i][k] over half-turn m,
+ * for the plan's basis (FP64 pseudo-inverse on the host; a rank-deficient B
+ * is RT_E_ARG).  Device g [Ntheta][Nz][Ns], f_out [Nz][N][N][K].  Needs
+ * Npi <= 64.  Allocates (Ntheta Nz Ns + 2 Nz N^2 Npi + Ntheta0 Nz Ns Npi)
+ * floats of temporaries for the call and blocks on `stream` before it
+ * returns. */
+int rt_fbp(const rt_plan *plan, const float *g, float *f_out, void *stream);
+
 /* ---- resumable job/step form of solve, for serving ---------------------
  * A job owns the solver state (f~, h1, h2, work arrays) on the device; the
  * caller still owns g and f.  rt_job_create runs the power iteration (if

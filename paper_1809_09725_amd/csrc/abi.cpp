@@ -87,3 +87,23 @@ extern "C" int shrink(const rt_plan *plan, float *pio, float lambda1, void *stre
     if ((rc = check_dev_ptr(pio, 4 * n4_of(p.g), "p"))) return rc;
     return launch_shrink(p, pio, lambda1, n4_of(p.g), (hipStream_t)stream);
 }
+
+extern "C" int rt_fbp_filter(const rt_plan *plan, const float *g, float *q, void *stream)
+{
+    int rc = prologue(plan);
+    if (rc) return rc;
+    const Plan &p = plan->impl;
+    if ((rc = check_dev_ptr(g, ng_of(p.g), "g"))) return rc;
+    if ((rc = check_dev_ptr(q, ng_of(p.g), "q"))) return rc;
+    return launch_fbp_filter(p, g, q, (hipStream_t)stream);
+}
+
+extern "C" int rt_fbp(const rt_plan *plan, const float *g, float *f_out, void *stream)
+{
+    int rc = prologue(plan);
+    if (rc) return rc;
+    const Plan &p = plan->impl;
+    if ((rc = check_dev_ptr(g, ng_of(p.g), "g"))) return rc;
+    if ((rc = check_dev_ptr(f_out, nf_of(p.g), "f_out"))) return rc;
+    return fbp_init(p, g, f_out, (hipStream_t)stream);
+}

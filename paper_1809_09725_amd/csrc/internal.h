@@ -144,6 +144,11 @@ inline size_t n4_of(const rt_geom &g) { return (size_t)g.Nz * g.N * g.N * g.Nt; 
 size_t job_state_bytes(const rt_geom &g);
 size_t plan_scratch_bytes(const rt_geom &g);
 size_t shadow_bytes(const rt_geom &g);   // BF16 shadow of f (synthesise-first plans)
+// FBP initial guess (fbp.hip): the Shepp-Logan filter of the projections, and
+// the whole guess (filter, half-turn back-projections, least-squares
+// coefficients; blocks on s before it returns)
+int launch_fbp_filter(const Plan &p, const float *g, float *q, hipStream_t s);
+int fbp_init(const Plan &p, const float *g, float *f, hipStream_t s);
 
 int check_geom(const rt_geom *g);
 int check_plan(const rt_plan *p);

@@ -29,7 +29,8 @@ EXPORTS = ("rt_plan_create", "rt_plan_destroy", "rt_plan_bytes", "rt_tables", "r
            "rt_adjoint", "tv_grad", "tv_div", "shrink", "solve", "rt_job_bytes",
            "rt_job_create", "rt_job_step", "rt_job_done", "rt_job_iters", "rt_job_report",
            "rt_job_checkpoint_bytes", "rt_job_checkpoint", "rt_job_restore", "rt_job_destroy",
-           "rt_dot", "rt_timing_enable", "rt_timing_reset", "rt_timing_read", "rt_last_error")
+           "rt_dot", "rt_timing_enable", "rt_timing_reset", "rt_timing_read", "rt_last_error",
+           "rt_fbp_filter", "rt_fbp")
 
 
 class RtError(RuntimeError):
@@ -95,6 +96,8 @@ def lib() -> ctypes.CDLL:
         "rt_job_restore": (c_int, [vp, vp, vp]),
         "rt_job_destroy": (None, [vp]),
         "rt_dot": (c_int, [vp, vp, sz, P(ctypes.c_double), vp]),
+        "rt_fbp_filter": (c_int, [vp, vp, vp, vp]),
+        "rt_fbp": (c_int, [vp, vp, vp, vp]),
         "rt_timing_enable": (c_int, [c_int]),
         "rt_timing_reset": (c_int, []),
         "rt_timing_read": (c_int, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
@@ -197,6 +200,16 @@ def rt_adjoint(plan: "Plan", g: torch.Tensor, f_out: torch.Tensor) -> None:
     _check(lib().rt_adjoint(plan.h, _ptr(g, plan.geom.g_shape, plan.device, "g"),
                             _ptr(f_out, plan.geom.f_shape, plan.device, "f_out"),
                             _stream(plan.device)))
+
+
+def rt_fbp_filter(plan: "Plan", g: torch.Tensor, q: torch.Tensor) -> None:
+    _check(lib().rt_fbp_filter(plan.h, _ptr(g, plan.geom.g_shape, plan.device, "g"),
+                               _ptr(q, plan.geom.g_shape, plan.device, "q"), _stream(plan.device)))
+
+
+def rt_fbp(plan: "Plan", g: torch.Tensor, f_out: torch.Tensor) -> None:
+    _check(lib().rt_fbp(plan.h, _ptr(g, plan.geom.g_shape, plan.device, "g"),
+                        _ptr(f_out, plan.geom.f_shape, plan.device, "f_out"), _stream(plan.device)))
 
 
 def tv_grad(plan: "Plan", f: torch.Tensor, lambda2: float, p: torch.Tensor) -> None:
@@ -312,6 +325,17 @@ class Plan:
     def adjoint(self, g, out=None):
         out = self._new(self.geom.f_shape) if out is None else out
         rt_adjoint(self, g, out)
+        return out
+
+    def fbp_filter(self, g, out=None):
+        out = self._new(self.geom.g_shape) if out is None else out
+        rt_fbp_filter(self, g, out)
+        return out
+
+    def fbp(self, g, out=None):
+        """FBP initial guess in coefficient form (blocks until it is ready)."""
+        out = self._new(self.geom.f_shape) if out is None else out
+        rt_fbp(self, g, out)
         return out
 
     def tv_grad(self, f, lambda2, out=None):
