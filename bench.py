@@ -41,7 +41,8 @@ KERNELS = ("k_project", "k_contract", "k_fold", "k_backproject", "k_grad_shrink"
            "k_div_update", "k_project_sf", "k_fold_mfma")
 SOURCES = {"k_project": "proj_pf.hip", "k_contract": "proj_pf.hip", "k_fold": "proj_pf.hip",
            "k_backproject": "backproject.hip", "k_grad_shrink": "tv.hip", "k_div_update": "tv.hip",
-           "k_project_sf": "proj_sf.hip", "k_fold_mfma": "proj_sf.hip"}
+           "k_project_sf": "proj_sf.hip", "k_fold_mfma": "proj_sf.hip",
+           "k_shepp_logan": "fbp.hip", "k_analysis": "fbp.hip"}
 
 
 def log(*a):
@@ -100,7 +101,47 @@ def algorithmic(kernel: str, G, sf: bool = False) -> tuple[str, float]:
         return "hbm", n0 * G.Nz * G.Ns * 4.0 * G.K + G.Ntheta * G.Nz * G.Ns * 12.0
     if kernel == "k_fold":          # read g, write g~
         return "hbm", G.Ntheta * G.Nz * G.Ns * 4.0 + n0 * G.Nz * G.Ns * 4.0 * G.K
+    if kernel == "k_shepp_logan":   # every output bin sums the Ns bins of its row
+        return "alu", 2.0 * G.Ntheta * G.Nz * G.Ns * G.Ns
+    if kernel == "k_analysis":      # read the Npi frames, write the K coefficients
+        return "hbm", nvox * 4.0 * (G.Npi + G.K)
     raise KeyError(kernel)
+
+
+def fbp_measure(plan, G, g) -> dict:
+    """The FBP initial guess (rt_fbp) on the workload's sinogram: wall time of
+    one blocking call after an untimed one, and its kernels.  The half-turn
+    back-projection runs the fold-sum and back-projection with Npi channels."""
+    import dataclasses
+
+    import torch
+
+    from paper_1809_09725_amd import rt4d
+    f0 = torch.empty(G.f_shape, device=g.device)
+    plan.fbp(g, out=f0)
+    torch.cuda.synchronize()
+    rt4d.timing_reset()
+    rt4d.timing_enable(True)
+    t0 = time.perf_counter()
+    plan.fbp(g, out=f0)
+    t1 = time.perf_counter()
+    rt4d.timing_enable(False)
+    Gm = dataclasses.replace(G, K=G.Npi, Nt=G.Npi)
+    kern = {}
+    for k, geom in (("k_shepp_logan", G), ("k_fold", Gm), ("k_backproject", Gm), ("k_analysis", G)):
+        ms, n = rt4d.timing_read(k)
+        if not n:
+            continue
+        b, w = algorithmic(k, geom)
+        peak = PEAK_HBM if b == "hbm" else PEAK_FP32_VALU
+        kern[k] = {"ms": round(ms, 4), "launches": n, "bound": b,
+                   "frac": round(w / (ms * 1e-3) / peak, 4)}
+    rt4d.timing_reset()
+    log("FBP initial guess: " + f"{(t1 - t0) * 1e3:.1f} ms, " +
+        ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in kern.items()))
+    return {"what": "FBP initial guess (rt_fbp): Shepp-Logan filter, one frame per half-turn, "
+                    "least-squares coefficients; blocking call incl. its temporaries",
+            "ms": round((t1 - t0) * 1e3, 3), "kernels": kern}
 
 
 def source_sha(kernel: str) -> str:
@@ -374,6 +415,8 @@ def main() -> int:
         "iters_per_s": round(1e3 / ms_step, 4),
         "roofline": roof, "kernels": kern,
     }
+    if not args.kernels_only:
+        out["fbp"] = fbp_measure(plan, G, g)
     if not args.no_cpu_baseline:
         # about 15 s of oracle work: 16 slices at 512^2 x 1800 angles, fewer for larger slices
         nsl = max(1, min(G.Nz, round(CPU_SLICES * (512 / G.N) ** 2 * 1800 / G.Ntheta)))
