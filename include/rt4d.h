@@ -158,6 +158,27 @@ typedef struct {
 int solve(const rt_plan *plan, const rt_solve_params *params, const float *g,
           float *f, rt_solve_report *report, void *stream);
 
+/* ---- out-of-core solve --------------------------------------------------
+ * The iteration of `solve`, for a volume whose state does not fit on the
+ * device.  g and f stay in host memory, and every iteration streams the
+ * volume through the device in z-slabs of at most `slab` slices, in
+ * increasing z (the slab decomposition of Sec. 7).  Slabs carry one halo
+ * slice on either side:
+ *   - f~ of the next slab's first slice, not yet updated (z-gradient);
+ *   - h2 of the previous slab's last slice, already updated (divergence).
+ * Every voxel therefore sees the operands of the in-core iteration, and the
+ * iterate is the one `solve` returns, bit for bit.
+ * Host g [Ntheta][Nz][Ns] and f [Nz][N][N][K] (in: start, out: result); phi
+ * and S as for rt_plan_create.  Plain form (FP32).
+ * Memory: pinned host copies of f, g and the state f~, h1, h2, and on the
+ * device one slab with its halos plus a plan per slab height.
+ * check_every and tol must be 0: there are no per-iteration monitors.  The
+ * report's residual and objective are taken at the final f by one more pass.
+ * rel_change is 0.  Uses `stream` and blocks until done. */
+int rt_solve_ooc(const rt_geom *geom, const double *phi, const double *S,
+                 const rt_solve_params *params, const float *g, float *f, int32_t slab,
+                 rt_solve_report *report, void *stream);
+
 /* ---- initial guess (Secs. 5-6: the iteration starts from an FBP) ---------
  * q = the projections convolved over the detector with the Shepp-Logan
  * kernel h(n) = -2 / (pi^2 (4 n^2 - 1)) (unit bin spacing; bins outside

@@ -182,16 +182,29 @@ int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hi
 int launch_shrink(const Plan &p, float *pio, float lambda1, size_t n4, hipStream_t s);
 // F = S f (time frames, planar)
 int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s);
+// The three TV steps below compute slices [zbeg, zend) of the plan's Nz
+// (zend < 0: all of them); the other slices only serve as z-neighbours, which
+// lets a z-slab with halo slices be processed exactly as inside the volume.
 // h2 <- shrink(h2 + sigma grad F), F = S f~; FP64 partial sum of |grad F| per block
 int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
-                       float lambda2, double *part, hipStream_t s);
+                       float lambda2, double *part, hipStream_t s, int zbeg = 0, int zend = -1);
 // f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; Ff = S f~;
 // partials |f+ - f|^2, |f+|^2; synthesise-first plans also refresh the BF16
 // shadow d_f16 of f~ (and bump shadow_gen)
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
-                      float *Ff, float tau, float lambda2, double *part, hipStream_t s);
+                      float *Ff, float tau, float lambda2, double *part, hipStream_t s,
+                      int zbeg = 0, int zend = -1);
 // sum over voxels and frames of |grad S f| (FP64 partials)
-int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s);
+int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s,
+                   int zbeg = 0, int zend = -1);
+
+// Step rule and job buffers of the solver (solve.cpp), shared with the
+// out-of-core driver (ooc.cpp)
+double plan_s_norm(const Plan &p);
+int job_power_iteration(Job &J, hipStream_t s);
+int job_alloc(Job &J);
+void job_free(Job &J);
+int solve_params_check(const rt_solve_params *prm);
 
 // Reductions and vector helpers (reduce.hip)
 int reduce_blocks(int nblocks_hint, size_t n);

@@ -274,6 +274,15 @@ struct CkptHeader {
 
 }  // namespace
 
+namespace rt {
+// the step rule and job buffers, for the out-of-core driver (ooc.cpp)
+double plan_s_norm(const Plan &p) { return s_norm(p); }
+int job_power_iteration(Job &J, hipStream_t s) { return power_iteration(J, s); }
+int job_alloc(Job &J) { return alloc_job(J); }
+void job_free(Job &J) { free_job(J); }
+int solve_params_check(const rt_solve_params *prm) { return check_params(prm); }
+}  // namespace rt
+
 extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec, size_t *bytes)
 {
     int rc = check_geom(geom);

@@ -117,21 +117,23 @@ __global__ __launch_bounds__(NT) void k_frames(const float *__restrict__ f,
 
 // MODE 0: p = grad F (store).  MODE 1: h2 <- shrink(h2 + sigma grad F).
 // MODE 2: no store.  With part != NULL each workgroup writes the FP64 sum of
-// |grad F| over its voxels and frames.
+// |grad F| over its voxels and frames.  Slices [zbeg, zend) of the Nz present
+// are computed (and summed); the others only serve as z-neighbours.
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float lambda2,
                                              float sigma, float lambda1, float *__restrict__ p,
-                                             double *__restrict__ part, int N, int Nz, int Nt)
+                                             double *__restrict__ part, int N, int Nz, int Nt,
+                                             int zbeg, int zend)
 {
     __shared__ double sh[NT / 64];
     const size_t plane = (size_t)N * N;
-    const size_t nitem = plane * ((Nz + ZC - 1) / ZC);
+    const size_t nitem = plane * ((zend - zbeg + ZC - 1) / ZC);
     double tvs = 0.0;
     // a work item is one (row, column) over ZC consecutive slices, so the
     // z-neighbour frames one slice reads are still in L2 when the next one
     // reads them as its own
     for (size_t it = (size_t)blockIdx.x * NT + threadIdx.x; it < nitem; it += (size_t)gridDim.x * NT)
-    for (int z = (int)(it / plane) * ZC, ze = min(Nz, z + ZC); z < ze; ++z) {
+    for (int z = zbeg + (int)(it / plane) * ZC, ze = min(zend, z + ZC); z < ze; ++z) {
         const size_t pv = it % plane;
         const int q = (int)(pv % N);
         const int r = (int)(pv / N);
@@ -181,6 +183,8 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
 // MODE 0: out = S^T div p.  MODE 1 (Fig. 2 steps 5-6):
 //   f+ = f - tau adj + tau S^T div h2;  f~ = 2 f+ - f;  f = f+;  Ff = S f~
 // with FP64 partials |f+ - f|^2 and |f+|^2 per workgroup when part != NULL.
+// Slices [zbeg, zend) of the Nz present are computed; the others only serve
+// as z-neighbours.
 template <int KT, int MODE>
 __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                                             const float *__restrict__ S, float lambda2,
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                                             float *__restrict__ ft, float *__restrict__ Ff,
                                             float tau, double *__restrict__ part,
                                             __bf16 *__restrict__ f16, int KP, int N, int Nz,
-                                            int K, int Nt)
+                                            int K, int Nt, int zbeg, int zend)
 {
     constexpr int KS = kstride(KT);
     extern __shared__ float sm[];
@@ -198,12 +202,12 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
     stage_S<KT>(S, K, Nt, sS);
     const size_t plane = (size_t)N * N;
     const size_t ntile = (plane + NT - 1) / NT;
-    const size_t ntask = ntile * ((Nz + ZC - 1) / ZC);
+    const size_t ntask = ntile * ((zend - zbeg + ZC - 1) / ZC);
     double dn2 = 0.0, fn2 = 0.0;
     // a task is NT consecutive voxels of a plane over ZC consecutive slices
     // (the z-neighbour plane of h2 is then still in L2)
     for (size_t task = blockIdx.x; task < ntask; task += gridDim.x)
-    for (int zz = (int)(task / ntile) * ZC, ze = min(Nz, zz + ZC); zz < ze; ++zz) {
+    for (int zz = zbeg + (int)(task / ntile) * ZC, ze = min(zend, zz + ZC); zz < ze; ++zz) {
         const size_t pv0 = (task % ntile) * NT;
         const size_t v0 = (size_t)zz * plane + pv0;
         const int nv = (int)std::min<size_t>(NT, plane - pv0);
@@ -335,18 +339,20 @@ int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s)
 }
 
 static int launch_grad_mode(const Plan &p, int mode, const char *name, const float *F, float *pout,
-                            float sigma, float lambda1, float lambda2, double *part, hipStream_t s)
+                            float sigma, float lambda1, float lambda2, double *part, hipStream_t s,
+                            int zbeg = 0, int zend = -1)
 {
-    if (p.g.Nz == 0) return RT_OK;
+    if (zend < 0) zend = p.g.Nz;
+    if (zend <= zbeg) return RT_OK;
     const unsigned nb = voxel_blocks(p.g);
     const rt_geom &g = p.g;
     KTimer kt(name, s);
     if (mode == 0)
-        hipLaunchKernelGGL(k_grad<0>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+        hipLaunchKernelGGL(k_grad<0>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
     else if (mode == 1)
-        hipLaunchKernelGGL(k_grad<1>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+        hipLaunchKernelGGL(k_grad<1>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
     else
-        hipLaunchKernelGGL(k_grad<2>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt);
+        hipLaunchKernelGGL(k_grad<2>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
@@ -360,22 +366,25 @@ int launch_tv_grad(const Plan &p, const float *f, float lambda2, float *pout, hi
 }
 
 int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
-                       float lambda2, double *part, hipStream_t s)
+                       float lambda2, double *part, hipStream_t s, int zbeg, int zend)
 {
-    return launch_grad_mode(p, 1, "k_grad_shrink", Ff, h2, sigma, lambda1, lambda2, part, s);
+    return launch_grad_mode(p, 1, "k_grad_shrink", Ff, h2, sigma, lambda1, lambda2, part, s, zbeg,
+                            zend);
 }
 
-int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s)
+int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s,
+                   int zbeg, int zend)
 {
     int rc = launch_frames(p, f, p.d_frames, s);
     if (rc) return rc;
-    return launch_grad_mode(p, 2, "k_tv_norm", p.d_frames, nullptr, 0.f, 0.f, lambda2, part, s);
+    return launch_grad_mode(p, 2, "k_tv_norm", p.d_frames, nullptr, 0.f, 0.f, lambda2, part, s,
+                            zbeg, zend);
 }
 
 template <int MODE>
 static void launch_div_t(const Plan &p, const float *pin, float lambda2, float *out,
                          const float *adj, float *ft, float *Ff, float tau, double *part,
-                         __bf16 *f16, hipStream_t s)
+                         __bf16 *f16, hipStream_t s, int zbeg, int zend)
 {
     const unsigned nb = voxel_blocks(p.g);
     const size_t lds = tv_lds(p);
@@ -383,7 +392,7 @@ static void launch_div_t(const Plan &p, const float *pin, float lambda2, float *
     const int KP = p.sf.KP;
 #define RT_DIV(KT) hipLaunchKernelGGL((k_div<KT, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, \
                                       lambda2, out, adj, ft, Ff, tau, part, f16, KP, g.N, g.Nz,   \
-                                      g.K, g.Nt)
+                                      g.K, g.Nt, zbeg, zend)
     switch (p.tv.KT) {
     case 8: RT_DIV(8); break;
     case 16: RT_DIV(16); break;
@@ -397,19 +406,22 @@ int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hi
 {
     if (p.g.Nz == 0) return RT_OK;
     KTimer kt("k_tv_div", s);
-    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, s);
+    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, s, 0,
+                    p.g.Nz);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
 
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
-                      float *Ff, float tau, float lambda2, double *part, hipStream_t s)
+                      float *Ff, float tau, float lambda2, double *part, hipStream_t s, int zbeg,
+                      int zend)
 {
-    if (p.g.Nz == 0) return RT_OK;
+    if (zend < 0) zend = p.g.Nz;
+    if (zend <= zbeg) return RT_OK;
     KTimer kt("k_div_update", s);
     __bf16 *f16 = p.form == RT_FORM_SF ? (__bf16 *)p.d_f16 : nullptr;
-    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, f16, s);
+    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, f16, s, zbeg, zend);
     kt.stop();
     RT_HIP(hipGetLastError());
     if (f16) ++p.shadow_gen;

@@ -30,7 +30,7 @@ EXPORTS = ("rt_plan_create", "rt_plan_destroy", "rt_plan_bytes", "rt_tables", "r
            "rt_job_create", "rt_job_step", "rt_job_done", "rt_job_iters", "rt_job_report",
            "rt_job_checkpoint_bytes", "rt_job_checkpoint", "rt_job_restore", "rt_job_destroy",
            "rt_dot", "rt_timing_enable", "rt_timing_reset", "rt_timing_read", "rt_last_error",
-           "rt_fbp_filter", "rt_fbp")
+           "rt_fbp_filter", "rt_fbp", "rt_solve_ooc")
 
 
 class RtError(RuntimeError):
@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         "rt_dot": (c_int, [vp, vp, sz, P(ctypes.c_double), vp]),
         "rt_fbp_filter": (c_int, [vp, vp, vp, vp]),
         "rt_fbp": (c_int, [vp, vp, vp, vp]),
+        "rt_solve_ooc": (c_int, [P(rt_geom), vp, vp, P(rt_solve_params), vp, vp, i32,
+                                 P(rt_solve_report), vp]),
         "rt_timing_enable": (c_int, [c_int]),
         "rt_timing_reset": (c_int, []),
         "rt_timing_read": (c_int, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
@@ -200,6 +202,36 @@ def rt_adjoint(plan: "Plan", g: torch.Tensor, f_out: torch.Tensor) -> None:
     _check(lib().rt_adjoint(plan.h, _ptr(g, plan.geom.g_shape, plan.device, "g"),
                             _ptr(f_out, plan.geom.f_shape, plan.device, "f_out"),
                             _stream(plan.device)))
+
+
+def solve_ooc(geom: "Geom", g: torch.Tensor, f: torch.Tensor, slab: int, phi=None, S=None,
+              device=None, **kw) -> dict:
+    """Out-of-core solve: g and f are host (CPU) float32 tensors, f is updated
+    in place; the volume streams through the GPU in z-slabs of `slab` slices."""
+    import numpy as np
+    for name, t, shape in (("g", g, geom.g_shape), ("f", f, geom.f_shape)):
+        if t.device.type != "cpu" or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CPU tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    keep = []
+
+    def host(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.c_void_p)
+
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                       torch.device(device).index or 0)
+    rep = rt_solve_report()
+    prm = make_params(**kw)
+    with torch.cuda.device(dev):
+        _check(lib().rt_solve_ooc(ctypes.byref(geom.c()), host(phi), host(S), ctypes.byref(prm),
+                                  ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                  int(slab), ctypes.byref(rep), _stream(dev)))
+    return rep.as_dict()
 
 
 def rt_fbp_filter(plan: "Plan", g: torch.Tensor, q: torch.Tensor) -> None:

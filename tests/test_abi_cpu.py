@@ -89,3 +89,29 @@ def test_null_handles():
     assert L.rt_job_step(None, 1, None) == rt4d.RT_E_ARG
     L.rt_plan_destroy(None)
     L.rt_job_destroy(None)
+
+
+def test_ooc_rejects_bad_arguments_before_any_launch():
+    """The out-of-core solve checks its arguments on the host first."""
+    L = rt4d.lib()
+    geom = rt4d.Geom(N=16, Nz=4, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
+    prm = rt4d.make_params(lambda1=1.0, lambda2=1.0, n_iter=1)
+    rep = rt4d.rt_solve_report()
+    buf = ctypes.c_void_p(1 << 20)   # never dereferenced: the checks fail first
+    rc = L.rt_solve_ooc(ctypes.byref(geom.c()), None, None, ctypes.byref(prm), buf, buf, 0,
+                        ctypes.byref(rep), None)
+    assert rc == rt4d.RT_E_ARG and "slab" in L.rt_last_error().decode()
+    prm2 = rt4d.make_params(lambda1=1.0, lambda2=1.0, n_iter=1, check_every=2)
+    rc = L.rt_solve_ooc(ctypes.byref(geom.c()), None, None, ctypes.byref(prm2), buf, buf, 2,
+                        ctypes.byref(rep), None)
+    assert rc == rt4d.RT_E_ARG
+    bad = rt4d.Geom(N=16, Nz=4, Ns=16, Ntheta=10, Npi=3, K=8, Nt=3)
+    rc = L.rt_solve_ooc(ctypes.byref(bad.c()), None, None, ctypes.byref(prm), buf, buf, 2,
+                        ctypes.byref(rep), None)
+    assert rc == rt4d.RT_E_SHAPE
+    rc = L.rt_solve_ooc(ctypes.byref(geom.c()), None, None, ctypes.byref(prm), None, None, 2,
+                        ctypes.byref(rep), None)
+    assert rc == rt4d.RT_E_ARG
+    empty = rt4d.Geom(N=16, Nz=0, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
+    assert L.rt_solve_ooc(ctypes.byref(empty.c()), None, None, ctypes.byref(prm), None, None, 2,
+                          ctypes.byref(rep), None) == rt4d.RT_OK
