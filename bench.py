@@ -19,6 +19,9 @@ per iteration), inputs resident in HBM.  Prints one JSON line on stdout.
         # serving form: a Poisson trace of jobs of mixed size served with the
         # precision form under continuous batching, against the plain FP32
         # solver one job at a time; prints its own JSON line
+  python bench.py --ooc 16 [--steps 4 --warmup 1]
+        # out-of-core form: the state in host memory, streamed through the GPU
+        # in z-slabs of 16 slices; prints its own JSON line
 """
 from __future__ import annotations
 
@@ -277,6 +280,59 @@ def serve_main(args) -> int:
     return 0
 
 
+def ooc_main(args) -> int:
+    """Out-of-core form: the iteration state stays in host memory and every
+    iteration streams the volume through the GPU in z-slabs (rt_solve_ooc).
+    Two calls of W and W + K iterations from the same start; their time
+    difference over K is the per-iteration cost (set-up, step rule and the
+    final report cancel)."""
+    import torch
+
+    from paper_1809_09725_amd import inputs, rt4d
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    W = WORKLOADS[args.workload]
+    G = workload_geom(args.workload)
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, W["n_ell"], seed=W["seed"],
+                             axis_range=(G.N / 64, G.N / 16),
+                             z_axis_range=(G.Nz / 16, G.Nz / 4), rho_range=(0.1, 0.5),
+                             speed_per_halfturn=G.N / 64, drift=W["drift"], sphere=W["sphere"])
+    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=W["seed"],
+                        device="cuda").cpu().contiguous()
+    torch.cuda.empty_cache()
+    log(f"out-of-core: workload {args.workload} {G}, slabs of {args.ooc} slices")
+    times = []
+    rep = None
+    for n in (args.warmup, args.warmup + args.steps):
+        f = torch.zeros(G.f_shape)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = rt4d.solve_ooc(G, g, f, args.ooc, lambda1=2.0 ** -9 * 940.0 ** 2, lambda2=4.0,
+                             n_iter=n, n_pow=20, seed=2)
+        times.append(time.perf_counter() - t0)
+        log(f"  {n} iterations: {times[-1]:.3f} s (residual {rep['residual']:.6g})")
+    ms_it = (times[1] - times[0]) * 1e3 / args.steps
+    nf, ng = G.Nz * G.N * G.N * G.K, G.Ntheta * G.Nz * G.Ns
+    nh2 = 4 * G.Nz * G.N * G.N * G.Nt
+    nslab = (G.Nz + args.ooc - 1) // args.ooc
+    h2d = 4.0 * (2 * nf + (nslab - 1) * G.N * G.N * G.K + nh2 + 2 * ng)
+    d2h = 4.0 * (2 * nf + nh2 + ng)
+    samples = 2.0 * G.Ntheta * G.Nz * G.Ns * G.N
+    out = {"metric": "out-of-core R_T+R_T* Gray-samples/s (state in host memory)",
+           "value": round(samples / (ms_it * 1e-3) / 1e9, 3),
+           "unit": "Gray-samples/s (1e9 ray-samples/s)", "higher_is_better": True, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_iter": round(ms_it, 3),
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": W["desc"], "slab": args.ooc, "slabs": nslab,
+                      "state": "pinned host memory; two device slab sets, three streams"},
+           "pcie": {"h2d_GB_per_iter": round(h2d / 1e9, 3), "d2h_GB_per_iter": round(d2h / 1e9, 3),
+                    "h2d_GBps": round(h2d / (ms_it * 1e-3) / 1e9, 2),
+                    "d2h_GBps": round(d2h / (ms_it * 1e-3) / 1e9, 2)},
+           "setup_s": round(times[0], 3)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +349,9 @@ def main() -> int:
     ap.add_argument("--kernels-only", action="store_true",
                     help="uniform random sinogram instead of the phantom (same kernels and "
                          "launch shapes; fewer auxiliary launches, for counter runs)")
+    ap.add_argument("--ooc", type=int, default=0, metavar="SLAB",
+                    help="out-of-core form: the state stays in host memory and every iteration "
+                         "streams the volume through the GPU in z-slabs of SLAB slices")
     ap.add_argument("--serve", action="store_true",
                     help="serving form: served precision-form trace vs the plain solver serial")
     ap.add_argument("--jobs", type=int, default=64)
@@ -318,6 +377,8 @@ def main() -> int:
         return 0
     if args.serve:
         return serve_main(args)
+    if args.ooc > 0:
+        return ooc_main(args)
 
     import torch
 

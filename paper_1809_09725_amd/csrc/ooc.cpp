@@ -15,10 +15,13 @@
 // iterate is the same bit for bit.
 //
 // Host state (pinned, allocated per call): copies of f and g, f~, h1, h2.
-// Device state (per call): one extended slab of f, f~, R*h1, the frames, h2,
-// and the slab's sinogram rows of g and h1, plus a plan per slab height.
-// Everything runs on the caller's stream in order, so each upload follows
-// the download it depends on without host synchronisation.
+// Device state (per call): two sets of one extended slab of f, f~, R*h1,
+// the frames and h2, and of the slab's sinogram rows of g and h1, plus a
+// plan per slab height.  Slab k uses set k & 1, and three streams overlap
+// the upload of slab k+1, the compute of slab k and the download of slab
+// k-1; events order each copy after what it reads or overwrites.  The lower
+// halo is copied on the device from the other set, so no upload waits for
+// the previous slab's download.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -129,21 +132,49 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
     std::memset(H1, 0, ng * sizeof(float));
     std::memset(H2, 0, nh2 * sizeof(float));
 
-    // device slab: slot 0 = lower halo, slots 1..SL own, slot SL+1 = upper halo
-    DevBuf fd, ftd, wd, ffd, h2d, h1d, gd, sd;
+    // device slabs, two of them (slab k uses set k & 1): slot 0 = lower
+    // halo, slots 1..SL own, slot SL+1 = upper halo
     const size_t slots = (size_t)SL + 2;
-    RT_HIP(hipMalloc(&fd.p, slots * vf * sizeof(float)));
-    RT_HIP(hipMalloc(&ftd.p, slots * vf * sizeof(float)));
-    RT_HIP(hipMalloc(&wd.p, slots * vf * sizeof(float)));
-    RT_HIP(hipMalloc(&ffd.p, slots * vfr * sizeof(float)));
-    RT_HIP(hipMalloc(&h2d.p, slots * vh2 * sizeof(float)));
     const size_t ngs = std::max<size_t>((size_t)Nth * SL * Ns, 1);
-    RT_HIP(hipMalloc(&h1d.p, ngs * sizeof(float)));
-    RT_HIP(hipMalloc(&gd.p, ngs * sizeof(float)));
+    DevBuf fd[2], ftd[2], wd[2], ffd[2], h2d[2], h1d[2], gd[2], sd;
+    for (int b = 0; b < 2; ++b) {
+        RT_HIP(hipMalloc(&fd[b].p, slots * vf * sizeof(float)));
+        RT_HIP(hipMalloc(&ftd[b].p, slots * vf * sizeof(float)));
+        RT_HIP(hipMalloc(&wd[b].p, slots * vf * sizeof(float)));
+        RT_HIP(hipMalloc(&ffd[b].p, slots * vfr * sizeof(float)));
+        RT_HIP(hipMalloc(&h2d[b].p, slots * vh2 * sizeof(float)));
+        RT_HIP(hipMalloc(&h1d[b].p, ngs * sizeof(float)));
+        RT_HIP(hipMalloc(&gd[b].p, ngs * sizeof(float)));
+    }
     RT_HIP(hipMalloc(&sd.p, ngs * sizeof(float)));
-    float *fD = (float *)fd.p, *ftD = (float *)ftd.p, *wD = (float *)wd.p, *FfD = (float *)ffd.p;
-    float *h2D = (float *)h2d.p, *h1D = (float *)h1d.p, *gD = (float *)gd.p, *sD = (float *)sd.p;
-    // every return waits for the stream before the buffers above are released
+    float *sD = (float *)sd.p;
+    // three streams (default priority): uploads, compute, downloads; events
+    // per slab set and per slab of the volume
+    const int nslab = (Nz + SL - 1) / SL;
+    struct Pipe {
+        hipStream_t st[3] = {nullptr, nullptr, nullptr};
+        std::vector<hipEvent_t> ev;
+        ~Pipe()
+        {
+            for (hipStream_t x : st)
+                if (x) (void)hipStreamSynchronize(x);
+            for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+            for (hipStream_t x : st)
+                if (x) (void)hipStreamDestroy(x);
+        }
+    } pipe;
+    for (auto &x : pipe.st) RT_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    // events: 0,1 upload done; 2,3 lower halo taken; 4,5 compute done;
+    // 6,7 download done (per set); 8 + s: slab s downloaded
+    pipe.ev.resize(8 + nslab);
+    for (auto &e : pipe.ev) {
+        RT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        RT_HIP(hipEventRecord(e, pipe.st[0]));   // complete at once: the first waits pass
+    }
+    hipEvent_t *evUp = &pipe.ev[0], *evHalo = &pipe.ev[2], *evComp = &pipe.ev[4];
+    hipEvent_t *evDown = &pipe.ev[6], *evSlab = &pipe.ev[8];
+    const hipStream_t sH = pipe.st[0], sC = pipe.st[1], sDn = pipe.st[2];
+    // every return waits for the streams before the buffers above are released
     struct SyncGuard {
         hipStream_t s;
         ~SyncGuard() { (void)hipStreamSynchronize(s); }
@@ -153,10 +184,15 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
     const float l1 = (float)P.lambda1, l2 = (float)P.lambda2;
     const size_t rowb = (size_t)Ns * sizeof(float), pitch = (size_t)Nz * rowb;
 
+    long k = 0;   // slab counter over all iterations
+    int Sprev = 0;
     for (int it = 0; it < P.n_iter; ++it)
-        for (int z0 = 0; z0 < Nz; z0 += SL) {
-            const int z1 = std::min(Nz, z0 + SL), S = z1 - z0;
-            const int lo = z0 > 0, hi = z1 < Nz;
+        for (int si = 0; si < nslab; ++si, ++k) {
+            const int z0 = si * SL, z1 = std::min(Nz, z0 + SL), S = z1 - z0;
+            const int lo = z0 > 0, hi = z1 < Nz, b = (int)(k & 1);
+            float *fD = (float *)fd[b].p, *ftD = (float *)ftd[b].p, *wD = (float *)wd[b].p;
+            float *FfD = (float *)ffd[b].p, *h2D = (float *)h2d[b].p;
+            float *h1D = (float *)h1d[b].p, *gD = (float *)gd[b].p;
             const Plan *po = nullptr, *pg = nullptr, *pd = nullptr;
             // projections on the own slices; the gradient on own + upper halo;
             // the divergence on lower halo + own + upper halo (so that the own
@@ -164,32 +200,52 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
             if ((rc = plans.get(S, &po)) || (rc = plans.get(S + hi, &pg)) ||
                 (rc = plans.get(lo + S + hi, &pd)))
                 return rc;
-            // upload: f, f~ (+ upper halo), h2 (+ lower halo, already updated), h1, g
-            RT_HIP(hipMemcpyAsync(fD + vf, F + z0 * vf, S * vf * sizeof(float), H2D, s));
-            RT_HIP(hipMemcpyAsync(ftD + vf, FT + z0 * vf, (S + hi) * vf * sizeof(float), H2D, s));
-            RT_HIP(hipMemcpyAsync(h2D + (1 - lo) * vh2, H2 + (z0 - lo) * vh2,
-                                  (lo + S) * vh2 * sizeof(float), H2D, s));
-            if ((rc = copy_rows(h1D, S * rowb, H1 + (size_t)z0 * Ns, pitch, S * rowb, Nth, H2D, s)) ||
-                (rc = copy_rows(gD, S * rowb, Gh + (size_t)z0 * Ns, pitch, S * rowb, Nth, H2D, s)))
+            // upload f, f~ (+ upper halo), h2, h1, g into set b once
+            //  - set b's previous slab (k-2) is downloaded,
+            //  - slab k-1 has copied its lower halo out of set b,
+            //  - this slab and the next were downloaded in the last iteration
+            RT_HIP(hipStreamWaitEvent(sH, evDown[b], 0));
+            RT_HIP(hipStreamWaitEvent(sH, evHalo[b ^ 1], 0));
+            RT_HIP(hipStreamWaitEvent(sH, evSlab[si], 0));
+            if (hi) RT_HIP(hipStreamWaitEvent(sH, evSlab[si + 1], 0));
+            RT_HIP(hipMemcpyAsync(fD + vf, F + z0 * vf, S * vf * sizeof(float), H2D, sH));
+            RT_HIP(hipMemcpyAsync(ftD + vf, FT + z0 * vf, (S + hi) * vf * sizeof(float), H2D, sH));
+            RT_HIP(hipMemcpyAsync(h2D + vh2, H2 + z0 * vh2, S * vh2 * sizeof(float), H2D, sH));
+            if ((rc = copy_rows(h1D, S * rowb, H1 + (size_t)z0 * Ns, pitch, S * rowb, Nth, H2D, sH)) ||
+                (rc = copy_rows(gD, S * rowb, Gh + (size_t)z0 * Ns, pitch, S * rowb, Nth, H2D, sH)))
                 return rc;
-            // the in-core step on the slab's own slices
-            if ((rc = launch_frames(*pg, ftD + vf, FfD + vfr, s))) return rc;
-            if ((rc = launch_forward(*po, ftD + vf, nullptr, CONTRACT_PROX, gD, h1D, sf, nullptr, s)))
+            RT_HIP(hipEventRecord(evUp[b], sH));
+            // compute: the lower halo is the updated h2 of the previous slab's
+            // last slice, still on the device in the other set
+            RT_HIP(hipStreamWaitEvent(sC, evUp[b], 0));
+            if (lo)
+                RT_HIP(hipMemcpyAsync(h2D, (float *)h2d[b ^ 1].p + (size_t)Sprev * vh2,
+                                      vh2 * sizeof(float), hipMemcpyDeviceToDevice, sC));
+            RT_HIP(hipEventRecord(evHalo[b], sC));
+            if ((rc = launch_frames(*pg, ftD + vf, FfD + vfr, sC))) return rc;
+            if ((rc = launch_forward(*po, ftD + vf, nullptr, CONTRACT_PROX, gD, h1D, sf, nullptr, sC)))
                 return rc;
-            if ((rc = launch_grad_shrink(*pg, FfD + vfr, h2D + vh2, sf, l1, l2, nullptr, s, 0, S)))
+            if ((rc = launch_grad_shrink(*pg, FfD + vfr, h2D + vh2, sf, l1, l2, nullptr, sC, 0, S)))
                 return rc;
-            if ((rc = launch_adjoint(*po, h1D, wD + vf, s))) return rc;
+            if ((rc = launch_adjoint(*po, h1D, wD + vf, sC))) return rc;
             const int e0 = 1 - lo;   // first slot of the extended slab
             if ((rc = launch_div_update(*pd, h2D + e0 * vh2, wD + e0 * vf, fD + e0 * vf, ftD + e0 * vf,
-                                        FfD + e0 * vfr, tf, l2, nullptr, s, lo, lo + S)))
+                                        FfD + e0 * vfr, tf, l2, nullptr, sC, lo, lo + S)))
                 return rc;
+            RT_HIP(hipEventRecord(evComp[b], sC));
             // download the slab's own slices
-            RT_HIP(hipMemcpyAsync(F + z0 * vf, fD + vf, S * vf * sizeof(float), D2H, s));
-            RT_HIP(hipMemcpyAsync(FT + z0 * vf, ftD + vf, S * vf * sizeof(float), D2H, s));
-            RT_HIP(hipMemcpyAsync(H2 + z0 * vh2, h2D + vh2, S * vh2 * sizeof(float), D2H, s));
-            if ((rc = copy_rows(H1 + (size_t)z0 * Ns, pitch, h1D, S * rowb, S * rowb, Nth, D2H, s)))
+            RT_HIP(hipStreamWaitEvent(sDn, evComp[b], 0));
+            RT_HIP(hipMemcpyAsync(F + z0 * vf, fD + vf, S * vf * sizeof(float), D2H, sDn));
+            RT_HIP(hipMemcpyAsync(FT + z0 * vf, ftD + vf, S * vf * sizeof(float), D2H, sDn));
+            RT_HIP(hipMemcpyAsync(H2 + z0 * vh2, h2D + vh2, S * vh2 * sizeof(float), D2H, sDn));
+            if ((rc = copy_rows(H1 + (size_t)z0 * Ns, pitch, h1D, S * rowb, S * rowb, Nth, D2H, sDn)))
                 return rc;
+            RT_HIP(hipEventRecord(evDown[b], sDn));
+            RT_HIP(hipEventRecord(evSlab[si], sDn));
+            Sprev = S;
         }
+    for (hipStream_t x : pipe.st) RT_HIP(hipStreamSynchronize(x));
+    float *fD = (float *)fd[0].p, *gD = (float *)gd[0].p;
 
     // report at the final f: |R_T f - g|^2 and the TV norm, slab by slab (the
     // TV of a slab's last slice reads the next slab's first slice)
