@@ -79,6 +79,11 @@ struct AdjCfg {
 struct SfCfg {
     int A = 1, ngroups = 0, BT = 1, nbt = 1, PCH = 32, CS = 20, NPP = 4, KP = 16;
     int UB = 1;           // bins per thread and class slot (BT = 512 UB covers Ns <= 2048)
+    // line parts: with NLP > 1 a workgroup walks N / NLP lines of its slice
+    // and stores partial ray sums, which k_sf_finish adds in a fixed order
+    // (large slices: the BF16 copy of one part then stays in the last-level
+    // cache while every class group of the slice streams it)
+    int NLP = 1;
     size_t lds = 0;
 };
 
@@ -112,6 +117,7 @@ struct Plan {
     size_t part_cap = 0;        // doubles in d_part
     double *d_red = nullptr;    // final FP64 sums (16 doubles)
     void *d_f16 = nullptr;      // synthesise-first: BF16 shadow of f, [Nz][N][N][KP]
+    float *d_psf = nullptr;     // synthesise-first, NLP > 1: partial ray sums [NLP][Ntheta][Nz][Ns]
     // bumped by every write of d_f16, so that a job knows whether the shadow
     // still holds its own f~
     mutable unsigned long long shadow_gen = 0;
@@ -144,6 +150,8 @@ inline size_t n4_of(const rt_geom &g) { return (size_t)g.Nz * g.N * g.N * g.Nt; 
 size_t job_state_bytes(const rt_geom &g);
 size_t plan_scratch_bytes(const rt_geom &g);
 size_t shadow_bytes(const rt_geom &g);   // BF16 shadow of f (synthesise-first plans)
+int sf_line_parts(const rt_geom &g);     // NLP of a synthesise-first plan
+size_t sf_partial_bytes(const rt_geom &g);   // its partial ray sums (0 when NLP = 1)
 // FBP initial guess (fbp.hip): the Shepp-Logan filter of the projections, and
 // the whole guess (filter, half-turn back-projections, least-squares
 // coefficients; blocks on s before it returns)
@@ -168,7 +176,8 @@ int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, f
                         float sigma, double *part, hipStream_t s);            // from d_f16
 int launch_to_bf16(const Plan &p, const float *f, hipStream_t s);            // f -> d_f16
 int launch_fold_mfma(const Plan &p, const float *g, hipStream_t s);
-unsigned sf_blocks(const Plan &p);
+unsigned sf_blocks(const Plan &p);     // projection workgroups (line parts included)
+unsigned sf_partials(const Plan &p);   // FP64 partials of the forward's h1 prox
 int sf_slots(int npp, int ub, int kb);   // classes per workgroup the kernel is built for
 // Dispatch on the plan's form: R_T (with the h1 prox when mode = CONTRACT_PROX) and R_T*
 int launch_forward(const Plan &p, const float *f, float *g, int mode, const float *gdata,

@@ -64,6 +64,20 @@ size_t shadow_bytes(const rt_geom &g)
     return (size_t)g.Nz * g.N * g.N * ((g.K + 15) / 16 * 16) * 2;
 }
 
+// a slice's BF16 copy in parts of at most 64 MiB of lines
+int sf_line_parts(const rt_geom &g)
+{
+    const size_t slice = (size_t)g.N * g.N * ((g.K + 15) / 16 * 16) * 2;
+    const size_t part = (size_t)64 << 20;
+    return (int)std::max<size_t>(1, std::min<size_t>({(slice + part - 1) / part, 16, (size_t)std::max(g.N, 1)}));
+}
+
+size_t sf_partial_bytes(const rt_geom &g)
+{
+    const int nlp = sf_line_parts(g);
+    return nlp > 1 ? (size_t)nlp * ng_of(g) * sizeof(float) : 0;
+}
+
 size_t job_state_bytes(const rt_geom &g)
 {
     return (2 * nf_of(g) + 2 * ng_of(g) + 5 * n4_of(g)) * sizeof(float);
@@ -220,6 +234,7 @@ static int configure(Plan &p)
         const int c4 = C.A * C.NPP / 4;
         C.CS = 4 * (c4 % 2 ? c4 : c4 + 1);
         C.lds = (size_t)(C.PCH + 2) * C.CS * sizeof(float);
+        C.NLP = sf_line_parts(g);
     }
 
     // device copies of the group tables
@@ -242,7 +257,7 @@ static void free_plan(Plan &p)
 {
     for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
                       (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_gcls_sf, (void *)p.d_gwalk_sf,
-                      (void *)p.d_scr, (void *)p.d_frames, p.d_f16,
+                      (void *)p.d_scr, (void *)p.d_frames, p.d_f16, (void *)p.d_psf,
                       (void *)p.d_part,
                       (void *)p.d_red})
         if (ptr) (void)hipFree(ptr);
@@ -284,6 +299,10 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
         const size_t sb = std::max<size_t>(shadow_bytes(p.g), 256);
         RT_HIP(hipMalloc(&p.d_f16, sb));
         p.bytes += sb;
+        if (const size_t pb = sf_partial_bytes(p.g)) {
+            RT_HIP(hipMalloc(&p.d_psf, pb));
+            p.bytes += pb;
+        }
     }
     // FP64 partials: h1 prox, shrink, primal update (two per workgroup), reductions
     p.part_cap = std::max<size_t>((size_t)1 << 18,

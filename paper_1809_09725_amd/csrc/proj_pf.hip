@@ -505,7 +505,7 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
 
 int forward_partials(const Plan &p)
 {
-    if (p.form == RT_FORM_SF) return (int)sf_blocks(p);
+    if (p.form == RT_FORM_SF) return (int)sf_partials(p);
     return p.fwd.nkc == 1 ? (int)project_blocks(p) : (int)row_blocks((long)p.g.Ntheta * p.g.Nz);
 }
 

@@ -38,16 +38,21 @@ __device__ inline unsigned short bf16_rne(float x)
 __device__ inline float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 struct SfEpi {
-    float *out;           // g (EPI_G) or h1 (EPI_PROX)
+    float *out;           // g (EPI_G) or h1 (EPI_PROX); with line parts: partial sums
     const float *gdata;   // measured sinogram (EPI_PROX)
     double *part;         // per-workgroup FP64 sum of (R f~ - g)^2, or NULL
+    size_t pstride;       // line parts: floats between the parts' partial sums
     float sigma;
     int prox, n0, Npi;
 };
 
 // Forward, synthesise-first.  Workgroup: slice z, a group of A classes of one
-// walk direction, bins [bt*BT, bt*BT + BT).  Thread t owns the rays (slot j,
-// bin bt*BT + t) for the A slots.  NPP: frame columns per class (Npi rounded
+// walk direction, bins [bt*BT, bt*BT + BT), and part lp of the NLP parts of
+// the slice's lines (NLP > 1: the ray sums over those lines are stored at
+// E.out + lp * E.pstride for k_sf_finish).  Consecutive workgroups take the
+// class groups of one part, so the part's BF16 lines are read while they are
+// still cached.  Thread t owns the rays (slot j, bin bt*BT + t) for the A
+// slots.  NPP: frame columns per class (Npi rounded
 // up to 4, the padding columns are zero); KB: MFMA k-steps of 16 channels.
 //
 // The frames F[c][pos] = sum_k Phi[i(c)][k] f_k(pos) of a chunk of PCH
@@ -61,7 +66,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const __bf16 *__restrict__ f16, const float *__restrict__ phi, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
-    int nbt, int PCH, int CS, unsigned nblocks, SfEpi E)
+    int nbt, int PCH, int CS, int NLP, unsigned nblocks, SfEpi E)
 {
     constexpr int KP = 16 * KB;
     constexpr int R = AS * UB;      // rays per thread: slot rho / UB, bin tid + ST * (rho % UB)
@@ -71,7 +76,10 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const int bt = lid % nbt;
     lid /= nbt;
     const int grp = lid % ngroups;
-    const int z = lid / ngroups;
+    lid /= ngroups;
+    const int lp = lid % NLP;
+    const int z = lid / NLP;
+    const int lbeg = (int)((long)lp * N / NLP), lend = (int)((long)(lp + 1) * N / NLP);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int walk = gwalk[grp];
     const int Npi = E.Npi;
@@ -131,13 +139,13 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const size_t lstep = walk == 0 ? (size_t)N * KP : (size_t)KP;
     const size_t pstep = walk == 0 ? (size_t)KP : (size_t)N * KP;
     const int nch = (N + PCH - 1) / PCH;
-    const int nsteps = N * nch;          // (line, chunk) steps
+    const int nsteps = (lend - lbeg) * nch;   // (line, chunk) steps of this part
 
     // B operand of one step for the wave's position tiles wave and wave + 8:
     // lane holds position c0 + tile*32 + lane%32, channels kb*16 + 8*(lane/32) + 0..7
     v8bf raw[2][KB];
     auto load_step = [&](int st) {
-        const int l = st / nch, c0 = (st % nch) * PCH;
+        const int l = lbeg + st / nch, c0 = (st % nch) * PCH;
         const __bf16 *src = fz + (size_t)l * lstep + 8 * (lane >> 5);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -149,12 +157,12 @@ __global__ __launch_bounds__(ST) void k_project_sf(
                 raw[h][kb] = in ? *(const v8bf *)(src + (size_t)pos * pstep + kb * 16) : v8bf{};
         }
     };
-    load_step(0);
+    if (nsteps > 0) load_step(0);
 
     int q0[R];
     float w0[R], w1[R];
     for (int st = 0; st < nsteps; ++st) {
-        const int l = st / nch, c0 = (st % nch) * PCH;
+        const int l = lbeg + st / nch, c0 = (st % nch) * PCH;
         if (c0 == 0) {   // ray positions on line l
             const double lc = (double)l - hN;
 #pragma unroll
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             const size_t o = ((size_t)i * Nz + z) * Ns + bo;
             const float v = acc[rho][r];
             if (!E.prox) {
-                E.out[o] = v;
+                E.out[o + lp * E.pstride] = v;
             } else {
                 const float d = v - E.gdata[o];
                 d2 += (double)d * (double)d;
@@ -246,6 +254,40 @@ __global__ __launch_bounds__(ST) void k_project_sf(
         const double sum = block_sum(d2, sh);
         if (tid == 0) E.part[blockIdx.x] = sum;
     }
+}
+
+// The line parts' partial ray sums added in part order, then stored as g or
+// taken into the h1 prox of Fig. 2 step 3 with the FP64 partial sums of
+// (R f~ - g)^2; rows grid-strided over a fixed number of workgroups.
+__global__ __launch_bounds__(NT) void k_sf_finish(const float *__restrict__ psf, int NLP,
+                                                  size_t ng, float *__restrict__ out,
+                                                  const float *__restrict__ gdata, int prox,
+                                                  float sigma, double *__restrict__ part)
+{
+    __shared__ double sh[NT / 64];
+    double d2 = 0.0;
+    const float inv1s = 1.f / (1.f + sigma);
+    for (size_t o = (size_t)blockIdx.x * NT + threadIdx.x; o < ng; o += (size_t)gridDim.x * NT) {
+        float v = psf[o];
+        for (int lp = 1; lp < NLP; ++lp) v += psf[(size_t)lp * ng + o];
+        if (!prox) {
+            out[o] = v;
+        } else {
+            const float d = v - gdata[o];
+            d2 += (double)d * (double)d;
+            out[o] = (out[o] + sigma * d) * inv1s;
+        }
+    }
+    if (part) {
+        const double s = block_sum(d2, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    }
+}
+
+unsigned sf_finish_blocks(const rt_geom &G)
+{
+    const size_t ng = ng_of(G);
+    return (unsigned)std::max<size_t>(1, std::min<size_t>((ng + NT - 1) / NT, 8192));
 }
 
 // BF16 shadow of f: [Nz][N][N][K] FP32 -> [Nz][N][N][KP] BF16 (round to
@@ -334,7 +376,7 @@ static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
     KTimer kt("k_project_sf", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(ST), C.lds, s, (const __bf16 *)p.d_f16, p.d_phi,
                        p.d_gcls_sf, p.d_gwalk_sf, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, C.A,
-                       C.ngroups, C.BT, C.nbt, C.PCH, C.CS, nb, E);
+                       C.ngroups, C.BT, C.nbt, C.PCH, C.CS, C.NLP, nb, E);
     kt.stop();
     return RT_OK;
 }
@@ -379,7 +421,14 @@ static int launch_sf_k(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
 
 }  // namespace
 
-unsigned sf_blocks(const Plan &p) { return (unsigned)p.g.Nz * p.sf.ngroups * p.sf.nbt; }
+unsigned sf_blocks(const Plan &p)
+{
+    return (unsigned)p.g.Nz * p.sf.ngroups * p.sf.nbt * p.sf.NLP;
+}
+
+// FP64 partials of the forward's h1 prox: one per projection workgroup, or one
+// per k_sf_finish workgroup when the lines come in parts
+unsigned sf_partials(const Plan &p) { return p.sf.NLP > 1 ? sf_finish_blocks(p.g) : sf_blocks(p); }
 
 int sf_slots(int npp, int ub, int kb)
 {
@@ -410,11 +459,14 @@ int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, f
     const rt_geom &G = p.g;
     if (G.Nz == 0) return RT_OK;
     SfEpi E{};
-    E.out = mode == CONTRACT_STORE ? g : h1;
+    float *dst = mode == CONTRACT_STORE ? g : h1;
+    const bool parts = p.sf.NLP > 1;
+    E.out = parts ? p.d_psf : dst;
     E.gdata = gdata;
-    E.part = part;
+    E.part = parts ? nullptr : part;
+    E.pstride = parts ? ng_of(G) : 0;
     E.sigma = sigma;
-    E.prox = mode == CONTRACT_PROX;
+    E.prox = !parts && mode == CONTRACT_PROX;
     E.n0 = p.n0;
     E.Npi = G.Npi;
     const unsigned nb = sf_blocks(p);
@@ -431,6 +483,14 @@ int launch_forward_sf16(const Plan &p, float *g, int mode, const float *gdata, f
     }
     if (rc) return rc;
     RT_HIP(hipGetLastError());
+    if (parts) {
+        KTimer kt("k_sf_finish", s);
+        hipLaunchKernelGGL(k_sf_finish, dim3(sf_finish_blocks(G)), dim3(NT), 0, s, p.d_psf,
+                           p.sf.NLP, ng_of(G), dst, gdata, mode == CONTRACT_PROX ? 1 : 0, sigma,
+                           part);
+        kt.stop();
+        RT_HIP(hipGetLastError());
+    }
     return RT_OK;
 }
 

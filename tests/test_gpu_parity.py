@@ -269,6 +269,31 @@ def test_precision_form_parity(G):
         assert e_f <= 3e-3 and e_a <= 3e-3
 
 
+def test_precision_form_line_parts():
+    """A 2048^2 slice with K = 32 holds 256 MiB in BF16, so each workgroup
+    walks a quarter of the lines and k_sf_finish adds the four partial ray
+    sums: forward within 3e-3 of the oracle on two slices, and the h1 prox
+    (with its FP64 residual monitor) of a short solve agrees with the plain
+    form's."""
+    G = rt4d.Geom(N=2048, Nz=2, Ns=64, Ntheta=2 * 4, Npi=2, K=32, Nt=2)
+    p = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    f = inputs.uniform(G.f_shape, 43)
+    e_f = rel(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f))
+    print(f"line parts: precision forward {e_f:.2e}", flush=True)
+    assert e_f <= 3e-3
+    g = T(inputs.uniform(G.g_shape, 44, 0.0, 1.0))
+    kw = dict(lambda1=0.5, lambda2=1.0, n_iter=3, tau=1e-4, sigma=1e-4, check_every=1)
+    f_sf = torch.zeros(G.f_shape, device=DEV)
+    r_sf = p.solve(g, f_sf, **kw)
+    f_pf = torch.zeros(G.f_shape, device=DEV)
+    r_pf = rt4d.Plan(G).solve(g, f_pf, **kw)
+    d = float(torch.linalg.vector_norm((f_sf - f_pf).double()) / torch.linalg.vector_norm(f_pf.double()))
+    print(f"line parts: solve f rel {d:.2e}, residual {r_sf['residual']:.6e} vs {r_pf['residual']:.6e}",
+          flush=True)
+    assert d <= 3e-3
+    assert abs(r_sf["residual"] - r_pf["residual"]) <= 3e-3 * r_pf["residual"]
+
+
 def test_precision_form_solve_c1():
     G = C1
     ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 3, seed=1, axis_range=(2, 8), rho_range=(0.5, 1.0),
