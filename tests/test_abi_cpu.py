@@ -78,6 +78,10 @@ def test_job_bytes_accounts_for_state():
     # the precision form adds the BF16 shadow of f~ (K rounded up to 16 channels)
     b16 = rt4d.rt_job_bytes(geom, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA)
     assert b16 - b == 128 * 512 * 512 * 16 * 2
+    # a 2048^2 slice at K = 32 is 256 MiB in BF16: four line parts of partial ray sums
+    c5 = rt4d.Geom(N=2048, Nz=32, Ns=2048, Ntheta=3600, Npi=12, K=32, Nt=12)
+    d5 = (rt4d.rt_job_bytes(c5, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA) - rt4d.rt_job_bytes(c5))
+    assert d5 == 32 * 2048 * 2048 * 32 * 2 + 4 * 3600 * 32 * 2048 * 4
     g5 = rt4d.Geom(N=64, Nz=2, Ns=64, Ntheta=80, Npi=8, K=5, Nt=8)
     assert (rt4d.rt_job_bytes(g5, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA) -
             rt4d.rt_job_bytes(g5)) == 2 * 64 * 64 * 16 * 2
