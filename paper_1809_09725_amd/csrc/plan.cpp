@@ -189,11 +189,13 @@ static int configure(Plan &p)
         wmax = std::max(wmax, (int)std::ceil(span) + 6);
     }
     B.WMAX = wmax;
-    // KC channels per window row, stride KC + 4 floats (an odd number of
-    // 16-byte groups); fewer classes per round when the window is wide
+    // KC channels per window row, stride KC + 4 floats; fewer classes per
+    // round when the window is wide.  9..12 channels take one 16-channel
+    // chunk: the same FMAs as two 8-channel chunks, with the ray geometry
+    // and the window staging done once
     {
         const int K4 = (g.K + 3) / 4 * 4;
-        B.KC = K4 >= 16 ? 16 : K4 >= 8 ? 8 : 4;
+        B.KC = K4 > 8 ? 16 : K4 > 4 ? 8 : 4;
         B.stride = B.KC + 4;
         while (B.CA > 1 && (size_t)B.CA * B.WMAX * B.stride * sizeof(float) > budget) B.CA /= 2;
         if ((size_t)B.CA * B.WMAX * B.stride * sizeof(float) > budget)
