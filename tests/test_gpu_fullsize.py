@@ -106,6 +106,35 @@ def test_c3_precision_sampled_slices():
                   (0, 63), 3e-3)
 
 
+def test_c3_precision_every_slice():
+    """All 64 slices of the 1024^2 x 64 workload: the precision form against
+    the plain FP32 form, slice by slice (the plain form is within 1e-5 of the
+    FP64 oracle on the sampled slices, so this is the precision form's error
+    to within that)."""
+    torch.cuda.set_device(DEV)
+    G = C3
+    f = torch.from_numpy(inputs.uniform(G.f_shape, 53)).to(DEV)
+    pf = rt4d.Plan(G, form=rt4d.RT_FORM_PF, prec=rt4d.RT_PREC_FP32)
+    ref = pf.forward(f)
+    ra = pf.adjoint(ref)
+    pf.close()
+    sf = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
+    got = sf.forward(f)
+    ga = sf.adjoint(ref)
+    torch.cuda.synchronize()
+    num = torch.linalg.vector_norm((got - ref).double(), dim=(0, 2))
+    den = torch.linalg.vector_norm(ref.double(), dim=(0, 2))
+    e = (num / den).cpu().numpy()
+    numa = torch.linalg.vector_norm((ga - ra).double(), dim=(1, 2, 3))
+    dena = torch.linalg.vector_norm(ra.double(), dim=(1, 2, 3))
+    ea = (numa / dena).cpu().numpy()
+    print(f"precision forward, 64 slices: rel {e.min():.3e} .. {e.max():.3e}; "
+          f"adjoint: rel {ea.min():.3e} .. {ea.max():.3e}", flush=True)
+    assert e.shape == (64,) and float(e.max()) <= 3e-3
+    assert float(ea.max()) <= 3e-3
+    sf.close()
+
+
 def test_c5_properties():
     """2048^2 x 32 slab, K = 32: adjoint identity in FP64, precision vs plain
     form, exact zeros in the empty slices."""
