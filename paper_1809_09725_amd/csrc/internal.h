@@ -84,6 +84,9 @@ struct SfCfg {
     // (large slices: the BF16 copy of one part then stays in the last-level
     // cache while every class group of the slice streams it)
     int NLP = 1;
+    // B operand staging: 0 = through registers, one step ahead; 3 = global ->
+    // LDS copies into a 3-stage ring per wave, two steps ahead (KB = 2)
+    int DS = 0;
     size_t lds = 0;
 };
 

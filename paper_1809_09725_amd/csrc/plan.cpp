@@ -237,6 +237,16 @@ static int configure(Plan &p)
         C.CS = 4 * (c4 % 2 ? c4 : c4 + 1);
         C.lds = (size_t)(C.PCH + 2) * C.CS * sizeof(float);
         C.NLP = sf_line_parts(g);
+        // the staged B operand (8 waves x 3 stages x 2 KB copies of 1 KiB) for
+        // 17..32 channels: there the per-step B loads are twice as large and
+        // their latency bounds the step (2048^2 slab: 315 -> 252 ms); with 16
+        // channels the ring's LDS costs more than it hides (512^2: one
+        // workgroup per CU instead of two, 18.5 -> 28.6 ms)
+        const size_t ring = (size_t)8 * 3 * 2 * kb * 1024;
+        if (kb == 2 && C.lds + ring <= 160 * 1024) {
+            C.DS = 3;
+            C.lds += ring;
+        }
     }
 
     // device copies of the group tables

@@ -61,7 +61,7 @@ struct SfEpi {
 // shadow of f.  They land in LDS position-major, row 1 + pos - c0 holding the
 // A*NPP frames of position pos, so that a ray's tap at one position is NPP/4
 // 16-byte reads, the access of the plain form's staged lines.
-template <int NPP, int KB, int AS, int UB>
+template <int NPP, int KB, int AS, int UB, int DS>
 __global__ __launch_bounds__(ST) void k_project_sf(
     const __bf16 *__restrict__ f16, const float *__restrict__ phi, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const double *__restrict__ ccos,
@@ -157,7 +157,40 @@ __global__ __launch_bounds__(ST) void k_project_sf(
                 raw[h][kb] = in ? *(const v8bf *)(src + (size_t)pos * pstep + kb * 16) : v8bf{};
         }
     };
-    if (nsteps > 0) load_step(0);
+    // DS > 0: the B operand goes global -> LDS directly, DS - 1 steps ahead,
+    // into a ring of DS stages private to the wave (NI copies of 64 x 16
+    // bytes per step).  The copies are issued from inline assembly, so the
+    // compiler does not treat them as LDS stores and adds no wait for them
+    // before the frame and tap reads; each step waits for its own copies with
+    // an explicit vmcnt.  Every copy reads a valid address (positions clamped
+    // to the slice, steps clamped to the last one), so the count per step is
+    // fixed; lanes outside the slice or the chunk are zeroed after the read.
+    constexpr int NI = 2 * KB;
+    char *wring = (char *)(fr + (size_t)(PCH + 2) * CS) + (size_t)wave * (DS > 0 ? DS : 1) * NI * 1024;
+    auto issue_step = [&](int st) {
+        const int sc = min(st, nsteps - 1);
+        const int l = lbeg + sc / nch, c0 = (sc % nch) * PCH;
+        const __bf16 *src = fz + (size_t)l * lstep + 8 * (lane >> 5);
+        char *dst = wring + (size_t)(st % (DS > 0 ? DS : 1)) * NI * 1024;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = wave + 8 * h;
+            const int pos = min(c0 + t * 32 + (lane & 31), N - 1);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const __bf16 *ga = src + (size_t)pos * pstep + kb * 16;
+                const unsigned la = (unsigned)(size_t)(dst + (h * KB + kb) * 1024);
+                asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :: "s"(__builtin_amdgcn_readfirstlane(la)), "v"(ga) : "memory", "m0");
+            }
+        }
+    };
+    if constexpr (DS > 0) {
+        if (nsteps > 0)
+            for (int d = 0; d < DS - 1; ++d) issue_step(d);
+    } else {
+        if (nsteps > 0) load_step(0);
+    }
 
     int q0[R];
     float w0[R], w1[R];
@@ -178,11 +211,27 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             }
         }
         v8bf bop[2][KB];
+        if constexpr (DS > 0) {
+            issue_step(st + DS - 1);   // into the stage step st - 1 has finished with
+            asm volatile("s_waitcnt vmcnt(%0)" :: "n"(NI * (DS - 1)) : "memory");
+            const char *src = wring + (size_t)(st % DS) * NI * 1024 + lane * 16;
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h) {
+                const int t = wave + 8 * h;
+                const bool in = t * 32 < PCH && c0 + t * 32 + (lane & 31) < N;
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) bop[h][kb] = raw[h][kb];
-        if (st + 1 < nsteps) load_step(st + 1);
+                for (int kb = 0; kb < KB; ++kb) {
+                    const v8bf x = *(const v8bf *)(src + (h * KB + kb) * 1024);
+                    bop[h][kb] = in ? x : v8bf{};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) bop[h][kb] = raw[h][kb];
+            if (st + 1 < nsteps) load_step(st + 1);
+        }
         v16f d0 = {}, d1 = {};
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
@@ -225,6 +274,8 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             }
         }
     }
+
+    if constexpr (DS > 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the last copies landed
 
     // ---- epilogue: every half-turn r of class a lands on bin b (even r) or Ns-1-b (odd r)
     double d2 = 0.0;
@@ -364,12 +415,12 @@ __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
     }
 }
 
-template <int NPP, int KB, int AS, int UB>
-static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
+template <int NPP, int KB, int AS, int UB, int DS>
+static int launch_sf_d(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
 {
     const rt_geom &G = p.g;
     const SfCfg &C = p.sf;
-    auto kern = k_project_sf<NPP, KB, AS, UB>;
+    auto kern = k_project_sf<NPP, KB, AS, UB, DS>;
     if (C.lds > 64 * 1024)
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)C.lds));
@@ -379,6 +430,16 @@ static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
                        C.ngroups, C.BT, C.nbt, C.PCH, C.CS, C.NLP, nb, E);
     kt.stop();
     return RT_OK;
+}
+
+// the staged B operand is planned for KB = 2 only
+template <int NPP, int KB, int AS, int UB>
+static int launch_sf_t(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb)
+{
+    if constexpr (KB == 2) {
+        if (p.sf.DS == 3) return launch_sf_d<NPP, KB, AS, UB, 3>(p, E, s, nb);
+    }
+    return launch_sf_d<NPP, KB, AS, UB, 0>(p, E, s, nb);
 }
 
 // AS slots for one bin per thread; UB bins per thread take AS / UB slots
