@@ -15,6 +15,13 @@ namespace rt {
 namespace {
 
 constexpr int BP_VPT = 4;     // pixels per thread (rows 8 apart)
+// Thread -> pixel: wave w of the tile takes columns 8w..8w+7 and lane l row
+// l / 8 of each 8-row step, so the 64 taps of one read instruction come from
+// an 8 x 8 pixel block.  Their detector positions then span few bins per
+// 16-lane pass of the LDS, which measured 4.1 cycles per 16-byte read on
+// sampled angles, against 7.2 for 2 rows x 32 columns.
+__device__ inline int bp_col(int tid) { return 8 * (tid >> 6) + (tid & 7); }
+__device__ inline int bp_row(int tid) { return (tid >> 3) & 7; }
 constexpr int BP_MAXCA = 16;  // classes staged per round, at most
 
 template <int KC, int VEC>
@@ -38,9 +45,9 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     const int k0 = kc * KC;
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
 
-    const int q = tq * 32 + (tid & 31);
+    const int q = tq * 32 + bp_col(tid);
     const double x = (double)q - hN;
-    const double y0 = (double)(tr * 32 + (tid >> 5)) - hN;   // rows y0 + 8j, j < BP_VPT
+    const double y0 = (double)(tr * 32 + bp_row(tid)) - hN;   // rows y0 + 8j, j < BP_VPT
     const double xlo = (double)(tq * 32) - hN, xhi = xlo + 31.0;
     const double ylo = (double)(tr * 32) - hN, yhi = ylo + 31.0;
 
@@ -126,7 +133,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     if (q >= N) return;
 #pragma unroll
     for (int j = 0; j < BP_VPT; ++j) {
-        const int r = tr * 32 + (tid >> 5) + 8 * j;
+        const int r = tr * 32 + bp_row(tid) + 8 * j;
         if (r >= N) continue;
         float *dst = out + (((size_t)z * N + r) * N + q) * K + k0;
 #pragma unroll
