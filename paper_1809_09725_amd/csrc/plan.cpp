@@ -178,6 +178,31 @@ static int configure(Plan &p)
     // waves share the CU's LDS and VALU.
     F.nth = F.KC == 16 && F.vec == 4 && !F.tl && F.A * F.BT > 1024 && g.N <= 512 ? 1024 : 512;
 
+    // Lane order of the forward waves. A wave's 64 rays are 64 consecutive bins
+    // of one class when BT is a multiple of 64; their positions on a line are
+    // spaced 1/|c| in [1, sqrt 2] apart, and each 16-byte tap read is served 16
+    // lanes at a time over 16 bank groups that repeat every 16 positions (the
+    // padded stride is an odd number of groups). Consecutive bins in a quarter
+    // of the wave span up to 22 positions, so some share a group. Ordering the
+    // 64 rays by (r / c) mod 16 and dealing them out in turn to the four
+    // quarters spreads each quarter's positions evenly over the 16 groups.
+    p.lperm.clear();
+    if (F.BT % 64 == 0) {
+        p.lperm.resize((size_t)n0 * 64);
+        for (int a = 0; a < n0; ++a) {
+            const double c = std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? p.T.ccos[a] : p.T.csin[a];
+            double ph[64];
+            int ord[64];
+            for (int r = 0; r < 64; ++r) {
+                ph[r] = std::fmod((double)r / c, 16.0);
+                if (ph[r] < 0) ph[r] += 16.0;
+                ord[r] = r;
+            }
+            std::stable_sort(ord, ord + 64, [&](int x, int y) { return ph[x] < ph[y]; });
+            for (int i = 0; i < 64; ++i) p.lperm[(size_t)a * 64 + (i % 4) * 16 + i / 4] = (uint8_t)ord[i];
+        }
+    }
+
     // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
     AdjCfg &B = p.adj;
     B.TQ = 32;
@@ -268,7 +293,7 @@ static int configure(Plan &p)
 static void free_plan(Plan &p)
 {
     for (void *ptr : {(void *)p.d_phi, (void *)p.d_S, (void *)p.d_ccos, (void *)p.d_csin,
-                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_gcls_sf, (void *)p.d_gwalk_sf,
+                      (void *)p.d_gcls, (void *)p.d_gwalk, (void *)p.d_lperm, (void *)p.d_gcls_sf, (void *)p.d_gwalk_sf,
                       (void *)p.d_scr, (void *)p.d_frames, p.d_f16, (void *)p.d_psf,
                       (void *)p.d_part,
                       (void *)p.d_red})
@@ -301,6 +326,7 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     if ((rc = dev_copy(&p.d_S, S32, &p.bytes))) return rc;
     if ((rc = dev_copy(&p.d_ccos, p.T.ccos, &p.bytes))) return rc;
     if ((rc = dev_copy(&p.d_csin, p.T.csin, &p.bytes))) return rc;
+    if (!p.lperm.empty() && (rc = dev_copy(&p.d_lperm, p.lperm, &p.bytes))) return rc;
     const size_t scr = std::max<size_t>(plan_scratch_bytes(p.g), 256);
     RT_HIP(hipMalloc(&p.d_scr, scr));
     p.bytes += scr;

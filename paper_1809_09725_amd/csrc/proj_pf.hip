@@ -104,12 +104,21 @@ struct FwdEpi {
 // (class, bin) of one group; P(a,z,b,k0..k0+KC) = sum over lines of the
 // linear interpolation between the two positions around the ray, times the
 // line spacing along the ray 1/c.
+// The ray a lane takes: its index pr in the tile, with the bin offset within
+// the aligned block of 64 (one wave, one class) reordered by the class's lane
+// map when there is one.
+__device__ inline int fwd_ray(int pr, int a, const unsigned char *__restrict__ lperm)
+{
+    return lperm && a >= 0 ? (pr & ~63) | (int)lperm[a * 64 + (pr & 63)] : pr;
+}
+
 template <int KC, int PPT, int PF, int VEC, bool TL, int NTH>
 __global__ __launch_bounds__(NTH) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
-    const int *__restrict__ gwalk, const double *__restrict__ ccos,
-    const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
-    int nbt, int nkc, int stride, int nbuf, unsigned nblocks, FwdEpi E)
+    const int *__restrict__ gwalk, const unsigned char *__restrict__ lperm,
+    const double *__restrict__ ccos, const double *__restrict__ csin, int N, int Nz, int Ns,
+    int K, int A, int ngroups, int BT, int nbt, int nkc, int stride, int nbuf, unsigned nblocks,
+    FwdEpi E)
 {
     extern __shared__ float lines[];   // nbuf buffers x [N + 2 slots][stride], slots = positions -1 .. N
     __shared__ double sh[NTH / 64];
@@ -130,10 +139,9 @@ __global__ __launch_bounds__(NTH) void k_project(
     float invc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int pr = tid + NTH * j;
-        const int slot = pr / BT;
-        const int b = bt * BT + pr % BT;
+        const int slot = (tid + NTH * j) / BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
+        const int b = bt * BT + fwd_ray(tid + NTH * j, a, lperm) % BT;
         base[j] = -1.0e9;   // far outside: both taps get weight 0
         slope[j] = 0.0;
         invc[j] = 0.f;
@@ -236,10 +244,9 @@ __global__ __launch_bounds__(NTH) void k_project(
     const float inv1s = 1.f / (1.f + E.sigma);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int pr = tid + NTH * j;
-        const int slot = pr / BT;
-        const int b = bt * BT + pr % BT;
+        const int slot = (tid + NTH * j) / BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
+        const int b = bt * BT + fwd_ray(tid + NTH * j, a, lperm) % BT;
         if (a < 0 || b >= Ns) continue;
         if (E.mode == EPI_P) {
             float *dst = P + (((size_t)a * Nz + z) * Ns + b) * K + k0;
@@ -388,7 +395,7 @@ static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipS
                                    (int)F.lds));
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(NTH), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
-                       p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
+                       p.d_lperm, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
                        F.nkc, F.stride, F.nbuf, nb, E);
     kt.stop();
     return RT_OK;

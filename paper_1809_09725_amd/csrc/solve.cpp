@@ -290,7 +290,7 @@ extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec, size_t *
     if (!bytes) return fail(RT_E_ARG, "bytes is NULL");
     const rt_geom &g = *geom;
     const size_t tables = ((size_t)g.Ntheta * g.K + (size_t)g.Nt * g.K) * sizeof(float) +
-                          (size_t)(g.Ntheta / g.Npi) * 2 * sizeof(double) + 64 * 1024;
+                          (size_t)(g.Ntheta / g.Npi) * (2 * sizeof(double) + 64) + 64 * 1024;
     const size_t parts = ((size_t)1 << 18) * sizeof(double) + 16 * sizeof(double);
     *bytes = tables + parts + plan_scratch_bytes(g) + n4_of(g) * sizeof(float) + job_state_bytes(g) +
              (form == RT_FORM_SF ? shadow_bytes(g) + sf_partial_bytes(g) : 0);
