@@ -113,7 +113,7 @@ struct Plan {
     double *d_csin = nullptr;
     int *d_gcls = nullptr;      // [ngroups][A], -1 = empty slot
     int *d_gwalk = nullptr;     // [ngroups]
-    uint8_t *d_lperm = nullptr; // [Ntheta0][64] forward lane -> bin offset in its block of 64; null: identity
+    uint8_t *d_lperm = nullptr; // [Ntheta0][64] forward lane -> bin offset in its block of 64
     int *d_gcls_sf = nullptr;   // class groups of the synthesise-first projector
     int *d_gwalk_sf = nullptr;
     float *d_scr = nullptr;     // [Ntheta0][Nz][Ns][K]: P (forward), g~ (adjoint)

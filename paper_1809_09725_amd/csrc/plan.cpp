@@ -186,8 +186,9 @@ static int configure(Plan &p)
     // of the wave span up to 22 positions, so some share a group. Ordering the
     // 64 rays by (r / c) mod 16 and dealing them out in turn to the four
     // quarters spreads each quarter's positions evenly over the 16 groups.
+    // (The plain form applies it only when BT is a multiple of 64.)
     p.lperm.clear();
-    if (F.BT % 64 == 0) {
+    {
         p.lperm.resize((size_t)n0 * 64);
         for (int a = 0; a < n0; ++a) {
             const double c = std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? p.T.ccos[a] : p.T.csin[a];
@@ -326,7 +327,7 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     if ((rc = dev_copy(&p.d_S, S32, &p.bytes))) return rc;
     if ((rc = dev_copy(&p.d_ccos, p.T.ccos, &p.bytes))) return rc;
     if ((rc = dev_copy(&p.d_csin, p.T.csin, &p.bytes))) return rc;
-    if (!p.lperm.empty() && (rc = dev_copy(&p.d_lperm, p.lperm, &p.bytes))) return rc;
+    if ((rc = dev_copy(&p.d_lperm, p.lperm, &p.bytes))) return rc;
     const size_t scr = std::max<size_t>(plan_scratch_bytes(p.g), 256);
     RT_HIP(hipMalloc(&p.d_scr, scr));
     p.bytes += scr;

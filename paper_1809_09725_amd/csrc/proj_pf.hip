@@ -105,8 +105,8 @@ struct FwdEpi {
 // linear interpolation between the two positions around the ray, times the
 // line spacing along the ray 1/c.
 // The ray a lane takes: its index pr in the tile, with the bin offset within
-// the aligned block of 64 (one wave, one class) reordered by the class's lane
-// map when there is one.
+// the aligned block of 64 (one wave, one class when BT is a multiple of 64)
+// reordered by the class's lane map when there is one.
 __device__ inline int fwd_ray(int pr, int a, const unsigned char *__restrict__ lperm)
 {
     return lperm && a >= 0 ? (pr & ~63) | (int)lperm[a * 64 + (pr & 63)] : pr;
@@ -395,7 +395,7 @@ static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipS
                                    (int)F.lds));
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(NTH), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
-                       p.d_lperm, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
+                       F.BT % 64 == 0 ? p.d_lperm : nullptr, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
                        F.nkc, F.stride, F.nbuf, nb, E);
     kt.stop();
     return RT_OK;

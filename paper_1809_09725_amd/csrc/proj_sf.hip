@@ -51,9 +51,10 @@ struct SfEpi {
 // the slice's lines (NLP > 1: the ray sums over those lines are stored at
 // E.out + lp * E.pstride for k_sf_finish).  Consecutive workgroups take the
 // class groups of one part, so the part's BF16 lines are read while they are
-// still cached.  Thread t owns the rays (slot j, bin bt*BT + t) for the A
-// slots.  NPP: frame columns per class (Npi rounded
-// up to 4, the padding columns are zero); KB: MFMA k-steps of 16 channels.
+// still cached.  Thread t owns the rays (slot j, bin bt*BT + t') for the A
+// slots, t' being t reordered within its wave by slot j's lane map.  NPP:
+// frame columns per class (Npi rounded up to 4, the padding columns are
+// zero); KB: MFMA k-steps of 16 channels.
 //
 // The frames F[c][pos] = sum_k Phi[i(c)][k] f_k(pos) of a chunk of PCH
 // positions are one v_mfma_f32_32x32x16_bf16 product per 32-position tile:
@@ -61,15 +62,24 @@ struct SfEpi {
 // shadow of f.  They land in LDS position-major, row 1 + pos - c0 holding the
 // A*NPP frames of position pos, so that a ray's tap at one position is NPP/4
 // 16-byte reads, the access of the plain form's staged lines.
+// The bin offset thread tid takes for class a: its own, reordered within its
+// wave's block of 64 bins by the class's lane map (the 16-lane tap reads at
+// positions 1/|c| apart then spread over the LDS bank groups; the row stride
+// CS is an odd number of 16-byte groups).
+__device__ inline int sf_bin(int tid, int a, const unsigned char *__restrict__ lperm)
+{
+    return a >= 0 ? (tid & ~63) | (int)lperm[a * 64 + (tid & 63)] : tid;
+}
+
 template <int NPP, int KB, int AS, int UB, int DS>
 __global__ __launch_bounds__(ST) void k_project_sf(
     const __bf16 *__restrict__ f16, const float *__restrict__ phi, const int *__restrict__ gcls,
-    const int *__restrict__ gwalk, const double *__restrict__ ccos,
+    const int *__restrict__ gwalk, const unsigned char *__restrict__ lperm, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int A, int ngroups, int BT,
     int nbt, int PCH, int CS, int NLP, unsigned nblocks, SfEpi E)
 {
     constexpr int KP = 16 * KB;
-    constexpr int R = AS * UB;      // rays per thread: slot rho / UB, bin tid + ST * (rho % UB)
+    constexpr int R = AS * UB;      // rays per thread: slot rho / UB, bin sf_bin(tid) + ST * (rho % UB)
     extern __shared__ float fr[];   // [PCH + 2][CS]; rows 0 and PCH + 1 stay zero
     __shared__ double sh[ST / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
@@ -91,8 +101,9 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     float invc[R];
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
-        const int j = rho / UB, bi = tid + ST * (rho % UB), b = bt * BT + bi;
+        const int j = rho / UB;
         const int a = j < A ? gcls[grp * A + j] : -1;
+        const int bi = sf_bin(tid, a, lperm) + ST * (rho % UB), b = bt * BT + bi;
         base[rho] = -1.0e9;   // far outside: never tapped
         slope[rho] = 0.0;
         invc[rho] = 0.f;
@@ -282,8 +293,9 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     const float inv1s = 1.f / (1.f + E.sigma);
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
-        const int j = rho / UB, bi = tid + ST * (rho % UB), b = bt * BT + bi;
+        const int j = rho / UB;
         const int a = j < A ? gcls[grp * A + j] : -1;
+        const int bi = sf_bin(tid, a, lperm) + ST * (rho % UB), b = bt * BT + bi;
         if (a < 0 || bi >= BT || b >= Ns) continue;
 #pragma unroll
         for (int r = 0; r < NPP; ++r) {
@@ -426,7 +438,7 @@ static int launch_sf_d(const Plan &p, const SfEpi &E, hipStream_t s, unsigned nb
                                    (int)C.lds));
     KTimer kt("k_project_sf", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(ST), C.lds, s, (const __bf16 *)p.d_f16, p.d_phi,
-                       p.d_gcls_sf, p.d_gwalk_sf, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, C.A,
+                       p.d_gcls_sf, p.d_gwalk_sf, p.d_lperm, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, C.A,
                        C.ngroups, C.BT, C.nbt, C.PCH, C.CS, C.NLP, nb, E);
     kt.stop();
     return RT_OK;
