@@ -264,7 +264,7 @@ def serve_main(args) -> int:
                                "1% noise",
                    "budget_gib": round(budget / 2**30, 1), "max_active": args.max_active,
                    "window": args.window},
-        "served": {"form": {"auto": "per job: SF (bf16 contraction, fp32 projection) when K > Npi, "
+        "served": {"form": {"auto": "per job: SF (bf16 contraction, fp32 projection) when K >= 2 Npi, "
                                     "else PF fp32", "sf": "SF (bf16 contraction, fp32 projection)",
                             "pf": "PF fp32"}[args.serve_form],
                    "jobs_sf": sum(serving.pick_form(s, args.serve_form) == "sf" for s in trace),

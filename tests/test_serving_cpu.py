@@ -126,8 +126,11 @@ def test_window_one_runs_shortest_remaining_first():
     assert seq == sorted(seq, key=lambda j: [1, 2, 0].index(j))
 
 
-def test_auto_form_picks_precision_only_when_k_exceeds_npi():
+def test_auto_form_picks_precision_only_for_at_least_two_channels_per_half_turn():
+    import dataclasses
     from paper_1809_09725_amd.serving import pick_form
     assert pick_form(spec(0, 0.0, K=16), "auto") == "sf"       # Npi = 8
+    assert pick_form(spec(0, 0.0, K=32), "auto") == "sf"
     assert pick_form(spec(0, 0.0, K=8), "auto") == "pf"
+    assert pick_form(dataclasses.replace(spec(0, 0.0, K=16), Npi=12, Ntheta=12 * 64), "auto") == "pf"
     assert pick_form(spec(0, 0.0, K=8), "sf") == "sf"
