@@ -33,6 +33,8 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     constexpr int stride = KC + 4;   // an odd number of 16-byte groups per bin
     extern __shared__ float win[];   // [CA][WMAX][stride]
     __shared__ int s_wlo[BP_MAXCA], s_w[BP_MAXCA];
+    __shared__ int s_wb[BP_MAXCA], s_we[BP_MAXCA];   // window rows [wb, we) hold bins 0..Ns-1
+    __shared__ long long s_goff[BP_MAXCA];           // element offset of window row 0's bin in gt
     __shared__ float s_inv[BP_MAXCA];   // 1 / max(|cos|, |sin|) of the staged classes
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int tq = lid % ntq;
@@ -74,21 +76,33 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             // one spare bin on each side: a pixel's s_p, formed incrementally
             // over its rows, may round an ulp outside [umin, umax]
             const int lo = (int)floor(umin) - 1;
+            const int wn = (int)floor(umax) + 3 - lo;
             s_wlo[tid] = lo;
-            s_w[tid] = (int)floor(umax) + 3 - lo;
+            s_w[tid] = wn;
+            s_wb[tid] = max(0, -lo);
+            s_we[tid] = min(wn, Ns - lo);
+            s_goff[tid] = (((long long)(a0 + tid) * Nz + z) * Ns + lo) * K + k0;
             s_inv[tid] = (float)(1.0 / fmax(fabs(cs), fabs(sn)));
         }
         __syncthreads();
         if (VEC == 4) {
-            constexpr int NQ = KC / 4;
-            for (int e = tid; e < nca * WMAX * NQ; e += NT) {
-                const int c = e / (WMAX * NQ), r = e % (WMAX * NQ);
-                const int w = r / NQ, kq = r % NQ;
-                const int b = s_wlo[c] + w;
+            // thread: channel quad kq of window rows tid / NQ + RS i, row =
+            // c WMAX + w; c = row / WMAX from the float reciprocal of
+            // (row + 1/2), which lies at least 1/(2 WMAX) from an integer and
+            // carries a relative error of 2^-23, so it is exact for fewer
+            // than 2^22 rows (a window that fits the LDS has under 2^14);
+            // the products fit 24 bits (w < WMAX, K <= 64)
+            constexpr int NQ = KC / 4, RS = NT / NQ;
+            const int kq = tid % NQ;
+            const bool kin = k0 + 4 * kq < K;
+            const float invw = 1.f / (float)WMAX;
+            for (int row = tid / NQ; row < nca * WMAX; row += RS) {
+                const int c = (int)(((float)row + 0.5f) * invw);
+                const int w = row - __mul24(c, WMAX);
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (w < s_w[c] && b >= 0 && b < Ns && k0 + 4 * kq < K)
-                    v = *(const float4 *)(gt + (((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + 4 * kq);
-                *(float4 *)(win + (c * WMAX + w) * stride + 4 * kq) = v;
+                if (kin && w >= s_wb[c] && w < s_we[c])
+                    v = *(const float4 *)(gt + s_goff[c] + (__mul24(w, K) + 4 * kq));
+                *(float4 *)(win + __mul24(row, stride) + 4 * kq) = v;
             }
         } else {
             for (int e = tid; e < nca * WMAX * KC; e += NT) {
@@ -116,7 +130,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
                 // triangle weights of the bins floor(u) and floor(u)+1
                 const float w0 = fmaxf(0.f, 1.f - fr * invc) * invc;
                 const float w1 = fmaxf(0.f, 1.f - (1.f - fr) * invc) * invc;
-                const float *t0 = win + (cw + (int)fl) * stride;
+                const float *t0 = win + __mul24(cw + (int)fl, stride);
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {
                     const float4 x0 = *(const float4 *)(t0 + k);
