@@ -359,7 +359,7 @@ def main() -> int:
     ap.add_argument("--iters", type=int, default=60)
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--serve-form", choices=("auto", "sf", "pf"), default="auto",
-                    help="form of the served jobs: auto = precision form when K > Npi, plain "
+                    help="form of the served jobs: auto = precision form when K >= 2 Npi, plain "
                          "FP32 otherwise")
     ap.add_argument("--window", type=int, default=2,
                     help="jobs with the least remaining work that get iterations queued at once")

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
 {
     constexpr int stride = KC + 4;   // an odd number of 16-byte groups per bin
     extern __shared__ float win[];   // [CA][WMAX][stride]
-    __shared__ int s_wlo[BP_MAXCA], s_w[BP_MAXCA];
+    __shared__ int s_wlo[BP_MAXCA];
     __shared__ int s_wb[BP_MAXCA], s_we[BP_MAXCA];   // window rows [wb, we) hold bins 0..Ns-1
     __shared__ long long s_goff[BP_MAXCA];           // element offset of window row 0's bin in gt
     __shared__ float s_inv[BP_MAXCA];   // 1 / max(|cos|, |sin|) of the staged classes
@@ -78,7 +78,6 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             const int lo = (int)floor(umin) - 1;
             const int wn = (int)floor(umax) + 3 - lo;
             s_wlo[tid] = lo;
-            s_w[tid] = wn;
             s_wb[tid] = max(0, -lo);
             s_we[tid] = min(wn, Ns - lo);
             s_goff[tid] = (((long long)(a0 + tid) * Nz + z) * Ns + lo) * K + k0;
@@ -105,14 +104,17 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
                 *(float4 *)(win + __mul24(row, stride) + 4 * kq) = v;
             }
         } else {
-            for (int e = tid; e < nca * WMAX * KC; e += NT) {
-                const int c = e / (WMAX * KC), r = e % (WMAX * KC);
-                const int w = r / KC, kk = r % KC;
-                const int b = s_wlo[c] + w;
+            // the same walk with one channel kk per thread (KC divides NT)
+            constexpr int RS = NT / KC;
+            const int kk = tid % KC;
+            const bool kin = k0 + kk < K;
+            const float invw = 1.f / (float)WMAX;
+            for (int row = tid / KC; row < nca * WMAX; row += RS) {
+                const int c = (int)(((float)row + 0.5f) * invw);
+                const int w = row - __mul24(c, WMAX);
                 float v = 0.f;
-                if (w < s_w[c] && b >= 0 && b < Ns && k0 + kk < K)
-                    v = gt[(((size_t)(a0 + c) * Nz + z) * Ns + b) * K + k0 + kk];
-                win[(c * WMAX + w) * stride + kk] = v;
+                if (kin && w >= s_wb[c] && w < s_we[c]) v = gt[s_goff[c] + (__mul24(w, K) + kk)];
+                win[__mul24(row, stride) + kk] = v;
             }
         }
         __syncthreads();
