@@ -191,8 +191,9 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             for (int kb = 0; kb < KB; ++kb) {
                 const __bf16 *ga = src + (size_t)pos * pstep + kb * 16;
                 const unsigned la = (unsigned)(size_t)(dst + (h * KB + kb) * 1024);
-                asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-                             :: "s"(__builtin_amdgcn_readfirstlane(la)), "v"(ga) : "memory", "m0");
+                // the LDS destination goes in m0, bound as an input operand
+                asm volatile("global_load_lds_dwordx4 %0, off"
+                             :: "v"(ga), "{m0}"(__builtin_amdgcn_readfirstlane(la)) : "memory");
             }
         }
     };
