@@ -35,7 +35,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     __shared__ int s_wlo[BP_MAXCA];
     __shared__ int s_wb[BP_MAXCA], s_we[BP_MAXCA];   // window rows [wb, we) hold bins 0..Ns-1
     __shared__ long long s_goff[BP_MAXCA];           // element offset of window row 0's bin in gt
-    __shared__ float s_inv[BP_MAXCA];   // 1 / max(|cos|, |sin|) of the staged classes
+    __shared__ float s_inv[BP_MAXCA], s_inv2[BP_MAXCA];   // 1/c and 1/c^2, c = max(|cos|, |sin|)
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int tq = lid % ntq;
     lid /= ntq;
@@ -81,7 +81,9 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             s_wb[tid] = max(0, -lo);
             s_we[tid] = min(wn, Ns - lo);
             s_goff[tid] = (((long long)(a0 + tid) * Nz + z) * Ns + lo) * K + k0;
-            s_inv[tid] = (float)(1.0 / fmax(fabs(cs), fabs(sn)));
+            const double ic = 1.0 / fmax(fabs(cs), fabs(sn));
+            s_inv[tid] = (float)ic;
+            s_inv2[tid] = (float)(ic * ic);
         }
         __syncthreads();
         if (VEC == 4) {
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
         __syncthreads();
         for (int c = 0; c < nca; ++c) {
             const double cs = ccos[a0 + c], sn = csin[a0 + c];
-            const float invc = s_inv[c];
+            const float invc = s_inv[c], invc2 = s_inv2[c], ic01 = invc - invc2;
             const int cw = c * WMAX - s_wlo[c];   // window row of bin b: cw + b
             // s_p in bin units for the thread's first row; rows 8 apart add 8 sin
             const double u0 = fma(x, cs, fma(y0, sn, hS)), du = 8.0 * sn;
@@ -129,9 +131,10 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
                 const double u = u0 + (double)j * du;
                 const double fl = floor(u);
                 const float fr = (float)(u - fl);
-                // triangle weights of the bins floor(u) and floor(u)+1
-                const float w0 = fmaxf(0.f, 1.f - fr * invc) * invc;
-                const float w1 = fmaxf(0.f, 1.f - (1.f - fr) * invc) * invc;
+                // triangle weights of the bins floor(u) and floor(u)+1,
+                // max(0, 1 - |s_b - s_p| / c) / c = max(0, 1/c - |s_b - s_p| / c^2)
+                const float w0 = fmaxf(0.f, fmaf(-fr, invc2, invc));
+                const float w1 = fmaxf(0.f, fmaf(fr, invc2, ic01));
                 const float *t0 = win + __mul24(cw + (int)fl, stride);
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {
