@@ -380,8 +380,8 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(the z-slab sharding across GPUs is described in DESIGN.md, not built)",
+        print("bench.py runs on one GPU only: it measures the single-GPU path "
+              "(the z-slab sharding across GPUs is designed, not built)",
               file=sys.stderr)
         return 2
     if args.copy_calib:
