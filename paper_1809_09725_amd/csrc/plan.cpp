@@ -186,22 +186,20 @@ static int configure(Plan &p)
     // of the wave span up to 22 positions, so some share a group. Ordering the
     // 64 rays by (r / c) mod 16 and dealing them out in turn to the four
     // quarters spreads each quarter's positions evenly over the 16 groups.
-    // (The plain form applies it only when BT is a multiple of 64.)
-    p.lperm.clear();
-    {
-        p.lperm.resize((size_t)n0 * 64);
-        for (int a = 0; a < n0; ++a) {
-            const double c = std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? p.T.ccos[a] : p.T.csin[a];
-            double ph[64];
-            int ord[64];
-            for (int r = 0; r < 64; ++r) {
-                ph[r] = std::fmod((double)r / c, 16.0);
-                if (ph[r] < 0) ph[r] += 16.0;
-                ord[r] = r;
-            }
-            std::stable_sort(ord, ord + 64, [&](int x, int y) { return ph[x] < ph[y]; });
-            for (int i = 0; i < 64; ++i) p.lperm[(size_t)a * 64 + (i % 4) * 16 + i / 4] = (uint8_t)ord[i];
+    // The plain form applies the order when BT is a multiple of 64, the
+    // precision form to each class slot's bins.
+    p.lperm.assign((size_t)n0 * 64, 0);
+    for (int a = 0; a < n0; ++a) {
+        const double c = std::fabs(p.T.ccos[a]) >= std::fabs(p.T.csin[a]) ? p.T.ccos[a] : p.T.csin[a];
+        double ph[64];
+        int ord[64];
+        for (int r = 0; r < 64; ++r) {
+            ph[r] = std::fmod((double)r / c, 16.0);
+            if (ph[r] < 0) ph[r] += 16.0;
+            ord[r] = r;
         }
+        std::stable_sort(ord, ord + 64, [&](int x, int y) { return ph[x] < ph[y]; });
+        for (int i = 0; i < 64; ++i) p.lperm[(size_t)a * 64 + (i % 4) * 16 + i / 4] = (uint8_t)ord[i];
     }
 
     // ---- adjoint: 32x32 pixel tiles, CA classes staged per round
