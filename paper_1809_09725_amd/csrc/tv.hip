@@ -90,7 +90,7 @@ __device__ inline void write_frames(const float *__restrict__ row, const float *
         float s = 0.f;
 #pragma unroll
         for (int k = 0; k < KT; ++k) s = fmaf(Sm[k], c[k], s);
-        Fz[(size_t)m * plane] = s;
+        __builtin_nontemporal_store(s, Fz + (size_t)m * plane);   // read next by the gradient
     }
 }
 
@@ -160,16 +160,19 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
                 pm[3 * plane] = gt;
             } else if (MODE == 1) {
                 float *pm = pz + (size_t)m * 4 * plane;
-                const float ax = fmaf(sigma, gx, pm[0]);
-                const float ay = fmaf(sigma, gy, pm[plane]);
-                const float az = fmaf(sigma, gz, pm[2 * plane]);
-                const float at = fmaf(sigma, gt, pm[3 * plane]);
+                // h2 of this voxel is read and written once here and next read
+                // after the back-projection has streamed through L2: streaming
+                // (non-temporal) accesses leave L2 to the frames' neighbour reads
+                const float ax = fmaf(sigma, gx, __builtin_nontemporal_load(pm));
+                const float ay = fmaf(sigma, gy, __builtin_nontemporal_load(pm + plane));
+                const float az = fmaf(sigma, gz, __builtin_nontemporal_load(pm + 2 * plane));
+                const float at = fmaf(sigma, gt, __builtin_nontemporal_load(pm + 3 * plane));
                 const float nrm = sqrtf(ax * ax + ay * ay + az * az + at * at);
                 const float sc = lambda1 <= 0.f ? 0.f : (nrm > lambda1 ? lambda1 / nrm : 1.f);
-                pm[0] = ax * sc;
-                pm[plane] = ay * sc;
-                pm[2 * plane] = az * sc;
-                pm[3 * plane] = at * sc;
+                __builtin_nontemporal_store(ax * sc, pm);
+                __builtin_nontemporal_store(ay * sc, pm + plane);
+                __builtin_nontemporal_store(az * sc, pm + 2 * plane);
+                __builtin_nontemporal_store(at * sc, pm + 3 * plane);
             }
             F0 = F1;
         }
@@ -251,16 +254,17 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
             const int n = nv * K;
             for (int e = threadIdx.x; e < n; e += NT) {
                 float *slot = rows + (e / K) * KS + e % K;
-                const float fo = fb[e];
-                const float fnw = fo - tau * ab[e] + tau * slot[0];
+                // f, R*h1 and f~ are touched once per iteration: streaming accesses
+                const float fo = __builtin_nontemporal_load(fb + e);
+                const float fnw = fo - tau * __builtin_nontemporal_load(ab + e) + tau * slot[0];
                 const float fx = 2.f * fnw - fo;
                 const float dd = fnw - fo;
                 if (part) {
                     dn2 += (double)dd * dd;
                     fn2 += (double)fnw * fnw;
                 }
-                fb[e] = fnw;
-                tb[e] = fx;
+                __builtin_nontemporal_store(fnw, fb + e);
+                __builtin_nontemporal_store(fx, tb + e);
                 slot[0] = fx;
             }
             __syncthreads();
