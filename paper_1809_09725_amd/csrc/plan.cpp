@@ -44,6 +44,11 @@ int check_geom(const rt_geom *g)
     if (g->N > 4096 || g->Ns > 8192 || g->K > 64 || g->Nt > 64 || (int64_t)g->Npi * g->K > 16384)
         return fail(RT_E_SHAPE, "size beyond the supported maximum (N<=4096, Ns<=8192, "
                     "K<=64, Nt<=64, Npi*K<=16384)");
+    // a staged line of the projector is held in the prefetch registers of its
+    // 512 threads: scalar staging (K % 4 != 0) covers lines of N <= 2048
+    // positions, float4 staging N <= 4096
+    if (g->N > 2048 && g->K % 4 != 0)
+        return fail(RT_E_SHAPE, "N=%d > 2048 needs K to be a multiple of 4 (got K=%d)", g->N, g->K);
     return RT_OK;
 }
 
@@ -167,6 +172,8 @@ static int configure(Plan &p)
                 F.nbuf = nbuf;
             }
     }
+    if (F.KC == 0)
+        return fail(RT_E_SHAPE, "no staged-line configuration of the projector for N=%d K=%d", g.N, g.K);
     F.pf = g.N * F.KC <= 4 * 4 * 512 ? 4 : 8;
     F.tl = g.N > 512;
     F.nkc = (g.K + F.KC - 1) / F.KC;

@@ -42,6 +42,9 @@ def test_no_oracle_in_the_library():
     (dict(K=0), rt4d.RT_E_SHAPE),
     (dict(Nz=-1), rt4d.RT_E_SHAPE),
     (dict(K=65), rt4d.RT_E_SHAPE),
+    # lines longer than 2048 positions are staged as float4 only: K % 4 == 0
+    (dict(N=3000, Ns=3000, K=15), rt4d.RT_E_SHAPE),
+    (dict(N=4096, Ns=64, K=5), rt4d.RT_E_SHAPE),
 ])
 def test_bad_geometry_rejected_before_any_launch(bad, code):
     g = dict(N=16, Nz=2, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
@@ -54,6 +57,14 @@ def test_bad_geometry_rejected_before_any_launch(bad, code):
     h = ctypes.c_void_p()
     rc = rt4d.lib().rt_plan_create(ctypes.byref(geom.c()), 0, 0, None, None, ctypes.byref(h))
     assert rc == code and not h.value
+
+
+def test_long_lines_accepted_with_float4_channels():
+    """Above N = 2048 the plan needs K % 4 == 0; such shapes pass the host checks."""
+    for n, k in ((3000, 16), (4096, 4), (2048, 15)):
+        geom = rt4d.Geom(N=n, Nz=1, Ns=64, Ntheta=8, Npi=2, K=k, Nt=2)
+        b = ctypes.c_size_t()
+        assert rt4d.lib().rt_job_bytes(ctypes.byref(geom.c()), 0, 0, ctypes.byref(b)) == rt4d.RT_OK
 
 
 def test_bad_enums_rejected():
