@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("n_iter", ctypes.c_int32), ("n_pow", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("route", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("mu", ctypes.c_double), ("variant", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -201,15 +201,22 @@ def power(g: Geom, n_pow: int = 20, seed: int = 0, route: str = "direct") -> flo
 
 def solve(g: Geom, data, *, lambda1: float, lambda2: float, n_iter: int, f0=None,
           tau: float = 0.0, sigma: float = 0.0, tol: float = 0.0, n_pow: int = 20,
-          check_every: int = 0, seed: int = 0, route: str = "direct", phi=None, S=None):
-    """Adapted Chambolle-Pock loop (Sec. 3, Fig. 2).  Returns (f, report dict)."""
+          check_every: int = 0, seed: int = 0, route: str = "direct", phi=None, S=None,
+          mu: float = 0.0, variant: str = "plain"):
+    """Adapted Chambolle-Pock loop (Sec. 3, Fig. 2).  Returns (f, report dict).
+
+    mu > 0 adds the uniformly convex term mu/2 |f|^2 (the primal step becomes
+    its prox); variant="accel" is the accelerated form with adaptive theta,
+    tau and sigma (the O(1/N^2) variant that Secs. 1 and 8 name)."""
     T = tables(g)
     phi = T["phi"] if phi is None else _f64(phi)
     S = T["S"] if S is None else _f64(S)
     data = _f64(data).reshape(g.Ntheta, g.Nz, g.Ns)
     f = np.zeros((g.Nz, g.N, g.N, g.K)) if f0 is None else _f64(f0).reshape(g.Nz, g.N, g.N, g.K).copy()
+    if variant not in ("plain", "accel"):
+        raise ValueError(variant)
     prm = _Params(lambda1, lambda2, tol, tau, sigma, n_iter, n_pow, check_every,
-                  1 if route == "folded" else 0, seed)
+                  1 if route == "folded" else 0, seed, mu, 1 if variant == "accel" else 0)
     rep = _Report()
     _L().or_solve(ctypes.byref(g.c()), _p(T["theta"]), _p(phi), _p(S), ctypes.byref(prm),
                   _p(data), _p(f), ctypes.byref(rep))

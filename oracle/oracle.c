@@ -41,7 +41,9 @@
  *   or_shrink            Sec. 3, prox of sigma F2* (pointwise projection)
  *   or_tv_norm           Sec. 2 eq. TV1 (value of the penalty, unweighted)
  *   or_power             power iteration for ||R_T|| (step-size rule)
- *   or_solve             Sec. 3 Fig. 2 (adapted Chambolle-Pock loop)
+ *   or_solve             Sec. 3 Fig. 2 (adapted Chambolle-Pock loop); with a
+ *                        uniformly convex term, its accelerated form (Sec. 1,
+ *                        Sec. 8: the O(1/N^2) variant of the method)
  *   or_shepp_logan      Secs. 5-6, the FBP initial guess: projections
  *                        convolved with the Shepp-Logan kernel
  */
@@ -63,6 +65,8 @@ typedef struct {
     double lambda1, lambda2, tol, tau, sigma;
     int32_t n_iter, n_pow, check_every, route;
     uint64_t seed;
+    double mu;          /* weight of the uniformly convex term mu/2 |f|^2 (0: none) */
+    int32_t variant;    /* 0: theta = 1, fixed steps; 1: accelerated (adaptive theta, tau, sigma) */
 } or_params;
 
 typedef struct {
@@ -541,14 +545,28 @@ double or_S_norm(const or_geom *g, const double *S)
  *   h2 <- shrink(h2 + sigma grad f~)
  *   f+ <- f - tau R* h1 + tau div h2
  *   f~ <- 2 f+ - f,  f <- f+
+ * With mu > 0 the primal function G of the splitting is mu/2 |f|^2 instead of
+ * zero (the model becomes uniformly convex, the condition under which Sec. 1
+ * and Sec. 8 quote the O(1/N^2) rate of the method), so the primal step is its
+ * prox:  f+ <- (f - tau R* h1 + tau div h2) / (1 + mu tau).
+ * variant 1 is the accelerated form of the primal-dual method for a
+ * uniformly convex G (Chambolle and Pock 2011, the algorithm with adaptive
+ * steps): after the primal step of iteration n, with the steps tau_n, sigma_n
+ * it used,
+ *   theta_n = 1 / sqrt(1 + 2 mu tau_n),
+ *   f~ <- f+ + theta_n (f+ - f),
+ *   tau_{n+1} = theta_n tau_n,  sigma_{n+1} = sigma_n / theta_n.
+ * (mu = 0 keeps theta_n = 1: the plain loop.)
  * Step sizes (unless given): L_R from or_power, L_G^2 = |S|^2 4 (d + l2^2 [Nt>1])
  * bounds |grad S|^2 (each forward difference has norm <= 2, d = number of
  * spatial axes longer than one sample), tau = sigma = 1/sqrt((1.01 L_R)^2 + L_G^2),
  * which keeps tau sigma |K|^2 < 1.  Every check_every iterations the monitors
  * are taken at the extrapolated point that the step just used:
- *   residual = |R f~ - g|, objective = 1/2 residual^2 + lambda1 TV(f~),
+ *   residual = |R f~ - g|, objective = 1/2 residual^2 + lambda1 TV(f~)
+ *   (+ mu/2 |f+|^2, at the point the primal step produced),
  *   rel_change = |f+ - f| / |f+|;  the loop stops when rel_change < tol.
- * After the loop the report's residual and objective are recomputed at f. */
+ * After the loop the report's residual and objective are recomputed at f;
+ * the report's tau and sigma are those of the step rule (tau_0, sigma_0). */
 int or_solve(const or_geom *g, const double *theta, const double *phi, const double *S,
              const or_params *prm, const double *gdata, double *f, or_report *rep)
 {
@@ -577,6 +595,7 @@ int or_solve(const or_geom *g, const double *theta, const double *phi, const dou
     double *adj = malloc(sizeof(double) * nf), *dv = malloc(sizeof(double) * nf);
     memcpy(ft, f, sizeof(double) * nf);
 
+    const double mu = prm->mu;
     int n = 0;
     for (n = 0; n < prm->n_iter; ++n) {
         const int check = prm->check_every > 0 && ((n + 1) % prm->check_every == 0);
@@ -597,18 +616,23 @@ int or_solve(const or_geom *g, const double *theta, const double *phi, const dou
         or_shrink(n4, h2, prm->lambda1);
         apply_Rt(g, route, theta, phi, h1, adj);
         or_tv_div(g, S, prm->lambda2, h2, dv);
+        const double th = prm->variant == 1 ? 1.0 / sqrt(1.0 + 2.0 * mu * tau) : 1.0;
         double dn2 = 0.0, fn2 = 0.0;
         for (size_t e = 0; e < nf; ++e) {
-            fn[e] = f[e] - tau * adj[e] + tau * dv[e];
+            fn[e] = (f[e] - tau * adj[e] + tau * dv[e]) / (1.0 + mu * tau);
             const double d = fn[e] - f[e];
             dn2 += d * d;
             fn2 += fn[e] * fn[e];
-            ft[e] = 2.0 * fn[e] - f[e];
+            ft[e] = prm->variant == 1 ? fn[e] + th * (fn[e] - f[e]) : 2.0 * fn[e] - f[e];
             f[e] = fn[e];
+        }
+        if (prm->variant == 1) {
+            tau = th * tau;
+            sigma = sigma / th;
         }
         if (check) {
             rep->residual = sqrt(res2);
-            rep->objective = 0.5 * res2 + prm->lambda1 * tvn;
+            rep->objective = 0.5 * res2 + prm->lambda1 * tvn + 0.5 * mu * fn2;
             rep->rel_change = fn2 > 0.0 ? sqrt(dn2 / fn2) : 0.0;
             if (prm->tol > 0.0 && rep->rel_change < prm->tol) { ++n; break; }
         }
@@ -618,7 +642,8 @@ int or_solve(const or_geom *g, const double *theta, const double *phi, const dou
     double res2 = 0.0;
     for (size_t e = 0; e < ng; ++e) { const double d = Rf[e] - gdata[e]; res2 += d * d; }
     rep->residual = sqrt(res2);
-    rep->objective = 0.5 * res2 + prm->lambda1 * or_tv_norm(g, S, prm->lambda2, f);
+    rep->objective = 0.5 * res2 + prm->lambda1 * or_tv_norm(g, S, prm->lambda2, f) +
+                     0.5 * mu * dot(nf, f, f);
     free(ft); free(fn); free(h1); free(Rf); free(h2); free(gr); free(adj); free(dv);
     return 0;
 }

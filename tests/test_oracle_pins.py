@@ -435,3 +435,116 @@ def test_solve_scalar_worked_example():
         f, _ = O.solve(g, np.ones((1, 1, 1)), lambda1=0.3, lambda2=1.0, n_iter=int(n),
                        tau=0.5, sigma=0.5)
         assert abs(f.item() - int(num) / int(den)) < 1e-15
+
+
+# ---------------------------------------- accelerated form (uniformly convex G)
+
+def test_accel_scalar_worked_example():
+    """Hand-worked iterates of the accelerated loop on the one-pixel problem
+    (golden file): adaptive theta, tau and sigma and the prox of mu/2 |f|^2."""
+    here = os.path.dirname(__file__)
+    rows = [l.split() for l in open(os.path.join(here, "golden", "cp_accel_scalar_hand.txt"))
+            if l.strip() and not l.startswith("#")]
+    g = Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1)
+    for n, val in rows:
+        f, rep = O.solve(g, np.ones((1, 1, 1)), lambda1=0.3, lambda2=1.0, n_iter=int(n),
+                         tau=0.5, sigma=0.5, mu=8.0, variant="accel")
+        assert abs(f.item() - float(val)) < 1e-15
+        assert rep["tau"] == 0.5 and rep["sigma"] == 0.5      # the step rule's values
+    # the plain loop on the same uniformly convex problem keeps theta = 1 and
+    # fixed steps: its first iterate is the same, its second is not
+    f1, _ = O.solve(g, np.ones((1, 1, 1)), lambda1=0.3, lambda2=1.0, n_iter=1, tau=0.5,
+                    sigma=0.5, mu=8.0)
+    f2, _ = O.solve(g, np.ones((1, 1, 1)), lambda1=0.3, lambda2=1.0, n_iter=2, tau=0.5,
+                    sigma=0.5, mu=8.0)
+    assert abs(f1.item() - 1 / 30) < 1e-16 and abs(f2.item() - 0.06476190476190476) > 1e-3
+
+
+def test_accel_with_mu_zero_is_the_plain_loop():
+    """mu = 0: theta_n = 1 and the steps stay fixed, so the accelerated form
+    is the loop of Fig. 2 (up to the rounding of f+ + 1 (f+ - f) vs 2 f+ - f)."""
+    g = TINY
+    data = RNG.uniform(-1, 1, (g.Ntheta, g.Nz, g.Ns))
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=60, tau=0.05, sigma=0.05, check_every=10)
+    fp, rp = O.solve(g, data, **kw)
+    fa, ra = O.solve(g, data, variant="accel", mu=0.0, **kw)
+    assert rel(fa, fp) < 1e-13
+    assert abs(ra["objective"] - rp["objective"]) < 1e-12 * rp["objective"]
+
+
+def test_tikhonov_limit_is_the_regularised_normal_equations():
+    """lambda1 = 0, mu > 0: both forms converge to the unique minimiser of
+    1/2 |Af - g|^2 + mu/2 |f|^2, i.e. (A^T A + mu I)^-1 A^T g (numpy solve)."""
+    g = TINY
+    A = dense_R(g)
+    data = RNG.uniform(-1, 1, (g.Ntheta, g.Nz, g.Ns))
+    mu = 1.0
+    ref = np.linalg.solve(A.T @ A + mu * np.eye(A.shape[1]), A.T @ data.ravel())
+    want = 0.5 * np.sum((A @ ref - data.ravel()) ** 2) + 0.5 * mu * ref @ ref
+    f, rep = O.solve(g, data, lambda1=0.0, lambda2=1.0, n_iter=4000, n_pow=200, mu=mu)
+    assert rel(f.ravel(), ref) < 1e-8
+    assert abs(rep["objective"] - want) < 1e-12 * want
+    # the accelerated form: |f_n - f*| = O(1/n)
+    errs = []
+    for n in (5000, 20000):
+        f, rep = O.solve(g, data, lambda1=0.0, lambda2=1.0, n_iter=n, n_pow=200, mu=mu,
+                         variant="accel")
+        errs.append(rel(f.ravel(), ref))
+    assert errs[1] < 3e-4 and errs[1] <= errs[0] / 3, errs
+    assert abs(rep["objective"] - want) < 1e-6 * want
+
+
+def test_accel_rate_and_minimiser_on_a_tv_problem():
+    """lambda1 > 0, mu > 0 (the uniformly convex case of the accelerated
+    method): the minimiser is unique; the plain loop converges to it, SLSQP on
+    the epigraph form agrees, and the accelerated iterates approach it at
+    least as fast as C/n (the O(1/N^2) bound on |f_n - f*|^2): every doubling
+    of n at least halves the error."""
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    rng = np.random.default_rng(5)
+    g = Geom(N=4, Nz=1, Ns=5, Ntheta=8, Npi=2, K=2, Nt=2)
+    lam1, lam2, mu = 0.05, 2.0, 0.5
+    A = dense_R(g)
+    nf = A.shape[1]
+    truth = rng.uniform(0, 1, nf)
+    data = (A @ truth + 0.05 * rng.normal(size=A.shape[0])).reshape(g.Ntheta, g.Nz, g.Ns)
+    star, _ = O.solve(g, data, lambda1=lam1, lambda2=lam2, n_iter=40000, n_pow=200, mu=mu)
+    star = star.ravel()
+    D = np.stack([O.tv_grad(g, np.eye(nf)[j].reshape(g.Nz, g.N, g.N, g.K), lam2).ravel()
+                  for j in range(nf)], axis=1)
+    nj = D.shape[0] // 4
+    Dj = D.reshape(nj, 4, nf)
+
+    def epi(x):
+        r = A @ x[:nf] - data.ravel()
+        return 0.5 * r @ r + lam1 * x[nf:].sum() + 0.5 * mu * x[:nf] @ x[:nf]
+
+    def epi_jac(x):
+        return np.concatenate([A.T @ (A @ x[:nf] - data.ravel()) + mu * x[:nf], lam1 * np.ones(nj)])
+
+    cons = [{"type": "ineq",
+             "fun": lambda x: x[nf:] ** 2 - np.einsum("jcn,n->jc", Dj, x[:nf]).__pow__(2).sum(1),
+             "jac": lambda x: np.hstack([-2 * np.einsum("jc,jcn->jn", np.einsum("jcn,n->jc", Dj, x[:nf]), Dj),
+                                         np.diag(2 * x[nf:])])},
+            {"type": "ineq", "fun": lambda x: x[nf:], "jac": lambda x: np.hstack([np.zeros((nj, nf)), np.eye(nj)])}]
+    x0 = np.concatenate([np.zeros(nf), np.ones(nj)])
+    res = scipy_opt.minimize(epi, x0, jac=epi_jac, constraints=cons, method="SLSQP",
+                             options={"maxiter": 3000, "ftol": 1e-16})
+
+    def obj(fv):
+        return 0.5 * np.sum((A @ fv - data.ravel()) ** 2) + 0.5 * mu * fv @ fv + \
+            lam1 * np.sum(np.linalg.norm((D @ fv).reshape(-1, 4), axis=1))
+
+    # the plain loop's limit is at least as good as SLSQP's point, and mu-strong
+    # convexity bounds their distance: |x - x*|^2 <= 2 (E(x) - E(x*)) / mu
+    e_star, e_ref = obj(star), obj(res.x[:nf])
+    assert e_star <= e_ref * (1 + 1e-9)
+    assert np.linalg.norm(res.x[:nf] - star) <= np.sqrt(2 * (e_ref - e_star) / mu) + 1e-6
+    assert rel(res.x[:nf], star) < 2e-3
+    errs = []
+    for n in (50, 100, 200, 400, 800, 1600):
+        f, _ = O.solve(g, data, lambda1=lam1, lambda2=lam2, n_iter=n, n_pow=200, mu=mu,
+                       variant="accel")
+        errs.append(rel(f.ravel(), star))
+    assert all(b <= 0.5 * a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-4
