@@ -132,16 +132,31 @@ int shrink(const rt_plan *plan, float *p, float lambda1, void *stream);
  * output j+1 of the stream with state `seed`, mapped to 2u-1, u = top 24
  * bits / 2^24) and L_G^2 = |S|_2^2 * 4 * (spatial axes longer than 1 +
  * lambda2^2 [Nt > 1]).  check_every > 0: FP64 monitors every so many
- * iterations, stop when rel_change < tol.  0 = fixed count. */
+ * iterations, stop when rel_change < tol.  0 = fixed count.
+ * mu >= 0: weight of a uniformly convex term mu/2 |f|^2 added to the model
+ * (0: the model of eq. lr12 as it stands).  variant: RT_CP_PLAIN (theta = 1,
+ * fixed steps) or RT_CP_ACCEL, the accelerated form of the primal-dual
+ * method for a uniformly convex primal term, whose O(1/N^2) rate Secs. 1
+ * and 8 of the paper name (Chambolle and Pock 2011, adaptive steps): after
+ * the primal step of iteration n, taken with tau_n and sigma_n,
+ *   theta_n = 1 / sqrt(1 + 2 mu tau_n),  f~ = f+ + theta_n (f+ - f),
+ *   tau_{n+1} = theta_n tau_n,  sigma_{n+1} = sigma_n / theta_n.
+ * With mu = 0 both variants are the plain loop. */
+typedef enum { RT_CP_PLAIN = 0, RT_CP_ACCEL = 1 } rt_cp_variant;
+
 typedef struct {
     double lambda1, lambda2, tol, tau, sigma;
     int32_t n_iter, n_pow, check_every;
     uint64_t seed;
+    double mu;
+    int32_t variant;
 } rt_solve_params;
 
 /* Report (FP64).  residual = |R_T f - g|, objective = 1/2 residual^2 +
- * lambda1 TV(f), taken at the returned f; rel_change = |f_n - f_{n-1}| / |f_n|
- * at the last monitored iteration (0 if none). */
+ * lambda1 TV(f) + mu/2 |f|^2, taken at the returned f; rel_change =
+ * |f_n - f_{n-1}| / |f_n| at the last monitored iteration (0 if none); tau
+ * and sigma are the initial steps (those of the step rule, or the given
+ * ones). */
 typedef struct {
     double L_R, L_G, tau, sigma, residual, objective, rel_change;
     int32_t iters_done;
@@ -150,8 +165,9 @@ typedef struct {
 /* The adapted Chambolle-Pock loop of Sec. 3, Fig. 2 with theta = 1:
  *   h1 <- (h1 + sigma (R_T f~ - g)) / (1 + sigma)
  *   h2 <- shrink(h2 + sigma grad_lambda2 S f~, lambda1)
- *   f+ <- f - tau R_T* h1 + tau S^T div_lambda2 h2
+ *   f+ <- (f - tau R_T* h1 + tau S^T div_lambda2 h2) / (1 + mu tau)
  *   f~ <- 2 f+ - f,   f <- f+
+ * (RT_CP_ACCEL: f~ and the steps as stated at rt_solve_params)
  * from f = f~ = f (input), h1 = 0, h2 = 0.  Device g, f (in: start, out:
  * result).  Allocates its state on the device for the duration of the call
  * and blocks until the report is ready. */

@@ -141,6 +141,7 @@ struct Job {
     float *work = nullptr;      // R_T* h1, coefficient shaped
     float *sino = nullptr;      // R_T f for the report, sinogram shaped
     double tau = 0, sigma = 0, L_R = 0, L_G = 0;
+    double tau0 = 0, sigma0 = 0;   // steps of the first iteration (the accelerated form adapts tau, sigma)
     int iters = 0;
     unsigned long long shadow_gen = ~0ull;   // plan shadow_gen when d_f16 last held this f~
     bool stopped = false;
@@ -202,12 +203,13 @@ int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s);
 // h2 <- shrink(h2 + sigma grad F), F = S f~; FP64 partial sum of |grad F| per block
 int launch_grad_shrink(const Plan &p, const float *Ff, float *h2, float sigma, float lambda1,
                        float lambda2, double *part, hipStream_t s, int zbeg = 0, int zend = -1);
-// f+ = f - tau*adj + tau*S^T div h2; f~ = 2 f+ - f; f = f+; Ff = S f~;
+// f+ = (f - tau*adj + tau*S^T div h2) * cinv; f~ = f+ + theta (f+ - f) (the
+// plain loop, cinv = theta = 1: f~ = 2 f+ - f); f = f+; Ff = S f~;
 // partials |f+ - f|^2, |f+|^2; synthesise-first plans also refresh the BF16
 // shadow d_f16 of f~ (and bump shadow_gen)
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
                       float *Ff, float tau, float lambda2, double *part, hipStream_t s,
-                      int zbeg = 0, int zend = -1);
+                      int zbeg = 0, int zend = -1, float cinv = 1.f, float theta = 1.f);
 // sum over voxels and frames of |grad S f| (FP64 partials)
 int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, hipStream_t s,
                    int zbeg = 0, int zend = -1);
@@ -219,6 +221,11 @@ int job_power_iteration(Job &J, hipStream_t s);
 int job_alloc(Job &J);
 void job_free(Job &J);
 int solve_params_check(const rt_solve_params *prm);
+// Steps of the accelerated form after an iteration taken with tau, sigma:
+// theta = 1 / sqrt(1 + 2 mu tau), tau <- theta tau, sigma <- sigma / theta
+// (theta = 1 for the plain loop).  Returns theta; cinv = 1 / (1 + mu tau) of
+// that iteration's primal prox.
+double cp_steps(const rt_solve_params &P, double *tau, double *sigma, double *cinv);
 
 // Reductions and vector helpers (reduce.hip)
 int reduce_blocks(int nblocks_hint, size_t n);

@@ -180,13 +180,16 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
         ~SyncGuard() { (void)hipStreamSynchronize(s); }
     } sync_guard{s};
     const auto H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost;
-    const float tf = (float)tau, sf = (float)sigma;
     const float l1 = (float)P.lambda1, l2 = (float)P.lambda2;
+    double tau_n = tau, sigma_n = sigma;   // the accelerated form adapts the steps per iteration
     const size_t rowb = (size_t)Ns * sizeof(float), pitch = (size_t)Nz * rowb;
 
     long k = 0;   // slab counter over all iterations
     int Sprev = 0;
-    for (int it = 0; it < P.n_iter; ++it)
+    for (int it = 0; it < P.n_iter; ++it) {
+        const float tf = (float)tau_n, sf = (float)sigma_n;
+        double cinv = 1.0;
+        const double theta = cp_steps(P, &tau_n, &sigma_n, &cinv);
         for (int si = 0; si < nslab; ++si, ++k) {
             const int z0 = si * SL, z1 = std::min(Nz, z0 + SL), S = z1 - z0;
             const int lo = z0 > 0, hi = z1 < Nz, b = (int)(k & 1);
@@ -230,7 +233,8 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
             if ((rc = launch_adjoint(*po, h1D, wD + vf, sC))) return rc;
             const int e0 = 1 - lo;   // first slot of the extended slab
             if ((rc = launch_div_update(*pd, h2D + e0 * vh2, wD + e0 * vf, fD + e0 * vf, ftD + e0 * vf,
-                                        FfD + e0 * vfr, tf, l2, nullptr, sC, lo, lo + S)))
+                                        FfD + e0 * vfr, tf, l2, nullptr, sC, lo, lo + S, (float)cinv,
+                                        (float)theta)))
                 return rc;
             RT_HIP(hipEventRecord(evComp[b], sC));
             // download the slab's own slices
@@ -244,12 +248,13 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
             RT_HIP(hipEventRecord(evSlab[si], sDn));
             Sprev = S;
         }
+    }
     for (hipStream_t x : pipe.st) RT_HIP(hipStreamSynchronize(x));
     float *fD = (float *)fd[0].p, *gD = (float *)gd[0].p;
 
     // report at the final f: |R_T f - g|^2 and the TV norm, slab by slab (the
     // TV of a slab's last slice reads the next slab's first slice)
-    double res2 = 0.0, tv = 0.0;
+    double res2 = 0.0, tv = 0.0, fsq = 0.0;
     for (int z0 = 0; z0 < Nz; z0 += SL) {
         const int z1 = std::min(Nz, z0 + SL), S = z1 - z0, hi = z1 < Nz;
         const Plan *po = nullptr, *pg = nullptr;
@@ -269,6 +274,14 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
             (rc = fetch_red(*pg, &v, s)))
             return rc;
         tv += v;
+        if (P.mu > 0) {   // |f|^2 of the uniformly convex term
+            const size_t nfs = (size_t)S * vf;
+            const int nbf = reduce_blocks(0, nfs);
+            if ((rc = launch_dot_partials(fD + vf, fD + vf, nfs, po->d_part, nbf, s)) ||
+                (rc = launch_finish(po->d_part, nbf, 1, po->d_red, s)) || (rc = fetch_red(*po, &v, s)))
+                return rc;
+            fsq += v;
+        }
     }
     RT_HIP(hipStreamSynchronize(s));
     std::memcpy(f_host, F, nf * sizeof(float));
@@ -278,7 +291,7 @@ int solve_ooc(const rt_geom &G, const double *phi, const double *Smat, const rt_
         rep->tau = tau;
         rep->sigma = sigma;
         rep->residual = std::sqrt(res2);
-        rep->objective = 0.5 * res2 + P.lambda1 * tv;
+        rep->objective = 0.5 * res2 + P.lambda1 * tv + 0.5 * P.mu * fsq;
         rep->rel_change = 0.0;
         rep->iters_done = P.n_iter;
         if (!std::isfinite(rep->residual) || !std::isfinite(rep->objective))

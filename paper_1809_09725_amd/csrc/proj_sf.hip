@@ -380,6 +380,13 @@ __global__ __launch_bounds__(NT) void k_to_bf16(const float *__restrict__ f,
 // A: lane holds bins row = lane%16, half-turns 4*(lane/16) + 0..3 of the
 // current 16-chunk; B: Phi rows of those half-turns, channel lane%16;
 // C: bins 4*(lane/16) + 0..3, channel lane%16.
+// Both operands are split into BF16 hi + lo parts and the three products
+// hi*hi + hi*lo + lo*hi are accumulated in FP32 (the lo*lo term is below
+// 2^-16 of the product): the sinogram fed to the adjoint is the dual h1 of
+// the data term, whose rounding to a single BF16 would put a 2^-9 relative
+// error straight into the primal update when few half-turns and classes
+// average it.  The fold is bound by its HBM traffic, so the two extra
+// products cost nothing measurable.
 __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
                                                   const float *__restrict__ phi,
                                                   float *__restrict__ gt, int Nz, int Ns, int K,
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
         const int kcol = kt * 16 + (lane & 15);
         v4f cacc = {0.f, 0.f, 0.f, 0.f};
         for (int r0 = 0; r0 < Npi; r0 += 16) {
-            v4s av, bh, bl;
+            v4s ah, al, bh, bl;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 4 * (lane >> 4) + q;
@@ -410,13 +417,16 @@ __global__ __launch_bounds__(NT) void k_fold_mfma(const float *__restrict__ g,
                     if (bin < Ns) gv = g[((size_t)i * Nz + z) * Ns + ((r & 1) ? Ns - 1 - bin : bin)];
                     if (kcol < K) pv = phi[(size_t)i * K + kcol];
                 }
-                av[q] = (short)bf16_rne(gv);
+                const unsigned short gh = bf16_rne(gv);
+                ah[q] = (short)gh;
+                al[q] = (short)bf16_rne(gv - bf16_val(gh));
                 const unsigned short h = bf16_rne(pv);
                 bh[q] = (short)h;
                 bl[q] = (short)bf16_rne(pv - bf16_val(h));
             }
-            cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bh, cacc, 0, 0, 0);
-            cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bl, cacc, 0, 0, 0);
+            cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, cacc, 0, 0, 0);
+            cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, cacc, 0, 0, 0);
+            cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, cacc, 0, 0, 0);
         }
         if (kcol < K) {
 #pragma unroll

@@ -134,6 +134,9 @@ int check_params(const rt_solve_params *prm)
     if (given && !(std::isfinite(prm->tau) && std::isfinite(prm->sigma)))
         return fail(RT_E_ARG, "tau and sigma must be finite");
     if (!given && prm->n_pow < 1) return fail(RT_E_ARG, "the default step rule needs n_pow >= 1");
+    if (!std::isfinite(prm->mu) || prm->mu < 0) return fail(RT_E_ARG, "mu must be finite and >= 0");
+    if (prm->variant != RT_CP_PLAIN && prm->variant != RT_CP_ACCEL)
+        return fail(RT_E_ARG, "unknown variant %d", (int)prm->variant);
     return RT_OK;
 }
 
@@ -173,6 +176,8 @@ int create_job(const rt_plan *plan, const rt_solve_params *prm, const float *g, 
             const double L = std::sqrt((1.01 * J.L_R) * (1.01 * J.L_R) + LG2);
             J.tau = J.sigma = 1.0 / L;
         }
+        J.tau0 = J.tau;
+        J.sigma0 = J.sigma;
     }
     // f~ = f, h1 = 0, h2 = 0, frames of f~
     if (!rc) rc = launch_copy(J.ft, f, nf_of(p.g), s);
@@ -193,10 +198,13 @@ int step_job(Job &J, int n, hipStream_t s)
 {
     const Plan &p = *J.plan;
     const rt_solve_params &P = J.prm;
-    const float tau = (float)J.tau, sigma = (float)J.sigma;
     const float l1 = (float)P.lambda1, l2 = (float)P.lambda2;
     int rc = RT_OK;
     for (int it = 0; it < n && J.iters < P.n_iter && !J.stopped; ++it) {
+        // this iteration's steps; the accelerated form adapts them afterwards
+        const float tau = (float)J.tau, sigma = (float)J.sigma;
+        double cinv = 1.0;
+        const double theta = cp_steps(P, &J.tau, &J.sigma, &cinv);
         const bool check = P.check_every > 0 && (J.iters + 1) % P.check_every == 0;
         double *pf = check ? p.d_part : nullptr;
         double *pg = check ? p.d_part + off_grad(p) : nullptr;
@@ -216,7 +224,9 @@ int step_job(Job &J, int n, hipStream_t s)
         if ((rc = launch_grad_shrink(p, J.Ff, J.h2, sigma, l1, l2, pg, s))) return rc;
         // steps 5-6: f+ = f - tau R_T* h1 + tau S^T div h2, f~ = 2 f+ - f
         if ((rc = launch_adjoint(p, J.h1, J.work, s))) return rc;
-        if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s))) return rc;
+        if ((rc = launch_div_update(p, J.h2, J.work, J.f, J.ft, J.Ff, tau, l2, pd, s, 0, -1,
+                                    (float)cinv, (float)theta)))
+            return rc;
         J.shadow_gen = p.shadow_gen;
         ++J.iters;
         if (check && p.g.Nz > 0) {
@@ -227,7 +237,7 @@ int step_job(Job &J, int n, hipStream_t s)
             double m[4];
             if ((rc = fetch(p, 4, m, s))) return rc;
             J.residual = std::sqrt(m[0]);
-            J.objective = 0.5 * m[0] + P.lambda1 * m[1];
+            J.objective = 0.5 * m[0] + P.lambda1 * m[1] + 0.5 * P.mu * m[3];
             J.rel_change = m[3] > 0 ? std::sqrt(m[2] / m[3]) : 0.0;
             if (!std::isfinite(J.residual) || !std::isfinite(J.objective) || !std::isfinite(J.rel_change))
                 return fail(RT_E_NONFINITE, "non-finite monitor at iteration %d", J.iters);
@@ -240,24 +250,26 @@ int step_job(Job &J, int n, hipStream_t s)
 int report_job(Job &J, rt_solve_report *rep, hipStream_t s)
 {
     const Plan &p = *J.plan;
-    const size_t ng = ng_of(p.g);
-    double m[2] = {0.0, 0.0};
+    const size_t ng = ng_of(p.g), nf = nf_of(p.g);
+    double m[3] = {0.0, 0.0, 0.0};
     if (p.g.Nz > 0) {
-        const int nbg = reduce_blocks(0, ng);
+        const int nbg = reduce_blocks(0, ng), nbf = reduce_blocks(0, nf);
         int rc = launch_forward(p, J.f, J.sino, CONTRACT_STORE, nullptr, nullptr, 0.f, nullptr, s);
         if (!rc) rc = launch_diff_sq_partials(J.sino, J.g, ng, p.d_part, nbg, s);
         if (!rc) rc = launch_finish(p.d_part, nbg, 1, p.d_red, s);
         if (!rc) rc = launch_tv_norm(p, J.f, (float)J.prm.lambda2, p.d_part + off_grad(p), s);
         if (!rc) rc = launch_finish(p.d_part + off_grad(p), (int)voxel_blocks(p.g), 1, p.d_red + 1, s);
-        if (!rc) rc = fetch(p, 2, m, s);
+        if (!rc && J.prm.mu > 0) rc = launch_dot_partials(J.f, J.f, nf, p.d_part, nbf, s);
+        if (!rc && J.prm.mu > 0) rc = launch_finish(p.d_part, nbf, 1, p.d_red + 2, s);
+        if (!rc) rc = fetch(p, J.prm.mu > 0 ? 3 : 2, m, s);
         if (rc) return rc;
     }
     rep->L_R = J.L_R;
     rep->L_G = J.L_G;
-    rep->tau = J.tau;
-    rep->sigma = J.sigma;
+    rep->tau = J.tau0;
+    rep->sigma = J.sigma0;
     rep->residual = std::sqrt(m[0]);
-    rep->objective = 0.5 * m[0] + J.prm.lambda1 * m[1];
+    rep->objective = 0.5 * m[0] + J.prm.lambda1 * m[1] + 0.5 * J.prm.mu * m[2];
     rep->rel_change = J.rel_change;
     rep->iters_done = J.iters;
     if (!std::isfinite(rep->residual) || !std::isfinite(rep->objective))
@@ -269,8 +281,9 @@ struct CkptHeader {
     char magic[8];
     rt_geom g;
     int32_t iters, stopped;
-    double tau, sigma, L_R, L_G, residual, objective, rel_change;
+    double tau, sigma, L_R, L_G, residual, objective, rel_change, tau0, sigma0;
 };
+constexpr char kMagic[9] = "RT4DCKP2";
 
 }  // namespace
 
@@ -281,6 +294,16 @@ int job_power_iteration(Job &J, hipStream_t s) { return power_iteration(J, s); }
 int job_alloc(Job &J) { return alloc_job(J); }
 void job_free(Job &J) { free_job(J); }
 int solve_params_check(const rt_solve_params *prm) { return check_params(prm); }
+
+double cp_steps(const rt_solve_params &P, double *tau, double *sigma, double *cinv)
+{
+    *cinv = P.mu > 0 ? 1.0 / (1.0 + P.mu * *tau) : 1.0;
+    if (P.variant != RT_CP_ACCEL || !(P.mu > 0)) return 1.0;
+    const double th = 1.0 / std::sqrt(1.0 + 2.0 * P.mu * *tau);
+    *tau *= th;
+    *sigma /= th;
+    return th;
+}
 }  // namespace rt
 
 extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec, size_t *bytes)
@@ -343,12 +366,13 @@ extern "C" int rt_job_checkpoint(const rt_job *job, void *host_buf, void *stream
     const rt_geom &g = J.plan->g;
     hipStream_t s = (hipStream_t)stream;
     CkptHeader h{};
-    std::memcpy(h.magic, "RT4DCKP1", 8);
+    std::memcpy(h.magic, kMagic, 8);
     h.g = g;
     h.iters = J.iters;
     h.stopped = J.stopped;
     h.tau = J.tau; h.sigma = J.sigma; h.L_R = J.L_R; h.L_G = J.L_G;
     h.residual = J.residual; h.objective = J.objective; h.rel_change = J.rel_change;
+    h.tau0 = J.tau0; h.sigma0 = J.sigma0;
     char *b = (char *)host_buf;
     std::memcpy(b, &h, sizeof h);
     b += sizeof h;
@@ -370,7 +394,7 @@ extern "C" int rt_job_restore(rt_job *job, const void *host_buf, void *stream)
     hipStream_t s = (hipStream_t)stream;
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof h);
-    if (std::memcmp(h.magic, "RT4DCKP1", 8) != 0 || std::memcmp(&h.g, &g, sizeof g) != 0)
+    if (std::memcmp(h.magic, kMagic, 8) != 0 || std::memcmp(&h.g, &g, sizeof g) != 0)
         return fail(RT_E_ARG, "checkpoint does not belong to a job of this geometry");
     const char *b = (const char *)host_buf + sizeof h;
     const size_t nf = nf_of(g) * sizeof(float), ng = ng_of(g) * sizeof(float);
@@ -386,6 +410,7 @@ extern "C" int rt_job_restore(rt_job *job, const void *host_buf, void *stream)
     J.stopped = h.stopped != 0;
     J.tau = h.tau; J.sigma = h.sigma; J.L_R = h.L_R; J.L_G = h.L_G;
     J.residual = h.residual; J.objective = h.objective; J.rel_change = h.rel_change;
+    J.tau0 = h.tau0; J.sigma0 = h.sigma0;
     J.shadow_gen = ~0ull;   // the BF16 shadow no longer holds this f~
     return RT_OK;
 }

@@ -186,6 +186,9 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
 // MODE 0: out = S^T div p.  MODE 1 (Fig. 2 steps 5-6):
 //   f+ = f - tau adj + tau S^T div h2;  f~ = 2 f+ - f;  f = f+;  Ff = S f~
 // with FP64 partials |f+ - f|^2 and |f+|^2 per workgroup when part != NULL.
+// With a uniformly convex term mu/2 |f|^2 (accel != 0) the primal step is its
+// prox, f+ = (f - tau adj + tau S^T div h2) * cinv, cinv = 1 / (1 + mu tau),
+// and the extrapolation takes the step's theta: f~ = f+ + theta (f+ - f).
 // Slices [zbeg, zend) of the Nz present are computed; the others only serve
 // as z-neighbours.
 template <int KT, int MODE>
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                                             const float *__restrict__ S, float lambda2,
                                             float *__restrict__ out, const float *__restrict__ adj,
                                             float *__restrict__ ft, float *__restrict__ Ff,
-                                            float tau, double *__restrict__ part,
+                                            float tau, float cinv, float theta, int accel,
+                                            double *__restrict__ part,
                                             __bf16 *__restrict__ f16, int KP, int N, int Nz,
                                             int K, int Nt, int zbeg, int zend)
 {
@@ -256,8 +260,14 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                 float *slot = rows + (e / K) * KS + e % K;
                 // f, R*h1 and f~ are touched once per iteration: streaming accesses
                 const float fo = __builtin_nontemporal_load(fb + e);
-                const float fnw = fo - tau * __builtin_nontemporal_load(ab + e) + tau * slot[0];
-                const float fx = 2.f * fnw - fo;
+                float fnw = fo - tau * __builtin_nontemporal_load(ab + e) + tau * slot[0];
+                float fx;
+                if (accel) {
+                    fnw *= cinv;
+                    fx = fnw + theta * (fnw - fo);
+                } else {
+                    fx = 2.f * fnw - fo;
+                }
                 const float dd = fnw - fo;
                 if (part) {
                     dn2 += (double)dd * dd;
@@ -387,16 +397,17 @@ int launch_tv_norm(const Plan &p, const float *f, float lambda2, double *part, h
 
 template <int MODE>
 static void launch_div_t(const Plan &p, const float *pin, float lambda2, float *out,
-                         const float *adj, float *ft, float *Ff, float tau, double *part,
-                         __bf16 *f16, hipStream_t s, int zbeg, int zend)
+                         const float *adj, float *ft, float *Ff, float tau, float cinv,
+                         float theta, double *part, __bf16 *f16, hipStream_t s, int zbeg, int zend)
 {
     const unsigned nb = voxel_blocks(p.g);
     const size_t lds = tv_lds(p);
     const rt_geom &g = p.g;
     const int KP = p.sf.KP;
+    const int accel = cinv != 1.f || theta != 1.f;
 #define RT_DIV(KT) hipLaunchKernelGGL((k_div<KT, MODE>), dim3(nb), dim3(NT), lds, s, pin, p.d_S, \
-                                      lambda2, out, adj, ft, Ff, tau, part, f16, KP, g.N, g.Nz,   \
-                                      g.K, g.Nt, zbeg, zend)
+                                      lambda2, out, adj, ft, Ff, tau, cinv, theta, accel, part,   \
+                                      f16, KP, g.N, g.Nz, g.K, g.Nt, zbeg, zend)
     switch (p.tv.KT) {
     case 8: RT_DIV(8); break;
     case 16: RT_DIV(16); break;
@@ -410,8 +421,8 @@ int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hi
 {
     if (p.g.Nz == 0) return RT_OK;
     KTimer kt("k_tv_div", s);
-    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, nullptr, nullptr, s, 0,
-                    p.g.Nz);
+    launch_div_t<0>(p, pin, lambda2, out, nullptr, nullptr, nullptr, 0.f, 1.f, 1.f, nullptr, nullptr,
+                    s, 0, p.g.Nz);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
@@ -419,13 +430,13 @@ int launch_tv_div(const Plan &p, const float *pin, float lambda2, float *out, hi
 
 int launch_div_update(const Plan &p, const float *h2, const float *adj, float *f, float *ft,
                       float *Ff, float tau, float lambda2, double *part, hipStream_t s, int zbeg,
-                      int zend)
+                      int zend, float cinv, float theta)
 {
     if (zend < 0) zend = p.g.Nz;
     if (zend <= zbeg) return RT_OK;
     KTimer kt("k_div_update", s);
     __bf16 *f16 = p.form == RT_FORM_SF ? (__bf16 *)p.d_f16 : nullptr;
-    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, part, f16, s, zbeg, zend);
+    launch_div_t<1>(p, h2, lambda2, f, adj, ft, Ff, tau, cinv, theta, part, f16, s, zbeg, zend);
     kt.stop();
     RT_HIP(hipGetLastError());
     if (f16) ++p.shadow_gen;

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "librt4d.so")
 RT_OK, RT_E_ARG, RT_E_SHAPE, RT_E_HIP, RT_E_OOM, RT_E_NONFINITE = 0, -1, -2, -3, -4, -5
 RT_FORM_PF, RT_FORM_SF = 0, 1
 RT_PREC_FP32, RT_PREC_BF16MFMA = 0, 1
+RT_CP_PLAIN, RT_CP_ACCEL = 0, 1
 
 EXPORTS = ("rt_plan_create", "rt_plan_destroy", "rt_plan_bytes", "rt_tables", "rt_forward",
            "rt_adjoint", "tv_grad", "tv_div", "shrink", "solve", "rt_job_bytes",
@@ -47,7 +48,8 @@ class rt_solve_params(ctypes.Structure):
     _fields_ = [("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("tol", ctypes.c_double), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("n_iter", ctypes.c_int32), ("n_pow", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("mu", ctypes.c_double), ("variant", ctypes.c_int32)]
 
 
 class rt_solve_report(ctypes.Structure):
@@ -262,8 +264,13 @@ def shrink(plan: "Plan", p: torch.Tensor, lambda1: float) -> None:
 
 def make_params(*, lambda1: float, lambda2: float, n_iter: int, tau: float = 0.0,
                 sigma: float = 0.0, tol: float = 0.0, n_pow: int = 20, check_every: int = 0,
-                seed: int = 0) -> rt_solve_params:
-    return rt_solve_params(lambda1, lambda2, tol, tau, sigma, n_iter, n_pow, check_every, seed)
+                seed: int = 0, mu: float = 0.0, variant: str = "plain") -> rt_solve_params:
+    """variant: "plain" (theta = 1, fixed steps) or "accel" (the accelerated
+    form with adaptive theta, tau, sigma for the uniformly convex model with
+    mu > 0)."""
+    v = {"plain": RT_CP_PLAIN, "accel": RT_CP_ACCEL}[variant]
+    return rt_solve_params(lambda1, lambda2, tol, tau, sigma, n_iter, n_pow, check_every, seed,
+                           mu, v)
 
 
 def solve(plan: "Plan", params: rt_solve_params, g: torch.Tensor, f: torch.Tensor) -> dict:

@@ -1,10 +1,12 @@
 """The out-of-core solve (rt_solve_ooc) against the in-core solve: the same
 iterate bit for bit, for every slab height from one slice to the whole
-volume, and the same step sizes and report."""
+volume, and the same step sizes and report; and against the FP64 oracle's
+solve, iterate within 1e-3."""
 import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from paper_1809_09725_amd import inputs, rt4d
 
 pytestmark = pytest.mark.gpu
@@ -85,3 +87,31 @@ def test_ooc_errors():
     assert e.value.code == rt4d.RT_E_ARG
     with pytest.raises(ValueError):
         rt4d.solve_ooc(G7, g.to(DEV), f0.clone(), 2, lambda1=1.0, lambda2=1.0, n_iter=1)
+
+
+@pytest.mark.parametrize("variant", ["plain", "accel"])
+def test_ooc_against_oracle(variant):
+    """Slabs of 3 slices (three slabs, two of them with both halos) for 8
+    iterations of the default step rule, plain and with the uniformly convex
+    term under the accelerated loop: the iterate within 1e-3 of the oracle's
+    (rel-L2, and the largest element error scaled by the largest value), the
+    objective within 1e-4."""
+    torch.cuda.set_device(DEV)
+    g, f0 = case(G7, 101)
+    kw = dict(lambda1=2.0 ** -9 * 48.0 ** 2, lambda2=4.0, n_iter=8, n_pow=20, seed=3)
+    if variant == "accel":
+        kw.update(mu=2.0, variant="accel")
+    f = f0.clone()
+    ro = rt4d.solve_ooc(G7, g, f, 3, **kw)
+    og = O.Geom(**G7.__dict__)
+    # the oracle takes the library's steps (its own power iteration agrees
+    # to 1e-5; parity is on the iteration)
+    fo, rr = O.solve(og, g.numpy(), f0=f0.numpy(), route="folded",
+                     **{**kw, "tau": ro["tau"], "sigma": ro["sigma"]})
+    a, b = f.numpy().astype(np.float64), fo
+    e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    m = float(np.abs(a - b).max() / np.abs(b).max())
+    print(f"{variant}: out-of-core vs oracle rel-L2 {e:.3e}, scaled max-abs {m:.3e}; objective "
+          f"{ro['objective']:.9e} vs {rr['objective']:.9e}", flush=True)
+    assert e <= 1e-3 and m <= 1e-3
+    assert abs(ro["objective"] - rr["objective"]) <= 1e-4 * abs(rr["objective"])

@@ -1,8 +1,11 @@
 """GPU parity of the HIP library (through the C ABI) with the FP64 oracle.
 
 Tolerances: tables bit-exact; operators rel-L2 <= 1e-5 (FP32 arithmetic
-against FP64); TV operators <= 1e-6; reconstructions after a fixed iteration
-count rel-L2 <= 1e-3."""
+against FP64) and <= 3e-3 with the BF16 contraction; TV operators <= 1e-6;
+reconstructions after a fixed iteration count rel-L2 <= 1e-3, in both forms.
+Every array comparison also bounds the largest element error: max |got - want|
+<= tol * max |want| (the same tolerance, scaled by the largest reference
+value), so that a few wrong elements cannot hide in the norm."""
 import numpy as np
 import pytest
 import torch
@@ -19,6 +22,18 @@ def rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def close(got, want, tol, what=""):
+    """rel-L2 <= tol and max |got - want| <= tol * max |want|; returns both."""
+    a = np.asarray(got, np.float64)
+    b = np.asarray(want, np.float64)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    e = rel(a, b)
+    m = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) if b.size else 0.0
+    print(f"  {what}: rel-L2 {e:.2e}, scaled max-abs {m:.2e} (tol {tol:.0e})", flush=True)
+    assert e <= tol and m <= tol, (what, e, m, tol)
+    return e, m
 
 
 def og(G):
@@ -73,10 +88,8 @@ def test_forward_adjoint_parity(G):
         s = inputs.uniform(G.g_shape, seed + 100)
         Rf = p.forward(T(f)).cpu().numpy()
         Rs = p.adjoint(T(s)).cpu().numpy()
-        e_f = rel(Rf, O.forward(og(G), f))
-        e_a = rel(Rs, O.adjoint(og(G), s))
-        print(f"  {maker}: forward {e_f:.2e} adjoint {e_a:.2e}")
-        assert e_f <= 1e-5 and e_a <= 1e-5
+        close(Rf, O.forward(og(G), f), 1e-5, f"{maker} forward")
+        close(Rs, O.adjoint(og(G), s), 1e-5, f"{maker} adjoint")
 
 
 def test_adjoint_identity_on_gpu():
@@ -108,11 +121,11 @@ def test_tv_parity(G):
     q = inputs.uniform(G.p_shape, 6)                  # library layout (Nz, Nt, 4, N, N)
     qo = np.ascontiguousarray(q.transpose(0, 3, 4, 1, 2))   # oracle layout (Nz, N, N, Nt, 4)
     pg = p.tv_grad(T(f), lam2).cpu().numpy()
-    assert rel(pg, O.tv_grad(og(G), f, lam2).transpose(0, 3, 4, 1, 2)) <= 1e-6
+    close(pg, O.tv_grad(og(G), f, lam2).transpose(0, 3, 4, 1, 2), 1e-6, "tv_grad")
     dv = p.tv_div(T(q), lam2).cpu().numpy()
-    assert rel(dv, O.tv_div(og(G), qo, lam2)) <= 1e-6
+    close(dv, O.tv_div(og(G), qo, lam2), 1e-6, "tv_div")
     sh = p.shrink(T(q), lam1).cpu().numpy()
-    assert rel(sh, O.shrink(qo, lam1).transpose(0, 3, 4, 1, 2)) <= 1e-6
+    close(sh, O.shrink(qo, lam1).transpose(0, 3, 4, 1, 2), 1e-6, "shrink")
     assert np.abs(p.shrink(T(q), 0.0).cpu().numpy()).max() == 0.0
 
 
@@ -130,11 +143,66 @@ def test_solve_parity_c1():
     f = torch.zeros(G.f_shape, device=DEV)
     rep = p.solve(T(g), f, **kw)
     fo, ro = O.solve(og(G), g, route="folded", **kw)
-    e = rel(f.cpu().numpy(), fo)
-    print(f"C1 solve rel {e:.2e}, objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
-    assert e <= 1e-3
+    print(f"C1 solve: objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
+    close(f.cpu().numpy(), fo, 1e-3, "C1 solve iterate")
     assert abs(rep["objective"] - ro["objective"]) <= 1e-4 * abs(ro["objective"])
     assert rep["iters_done"] == 50
+
+
+def c1_problem():
+    G = C1
+    ph = inputs.make_phantom(G.N, G.Nz, G.Npi, 3, seed=1, axis_range=(2, 8), rho_range=(0.5, 1.0),
+                             speed_per_halfturn=1.0)
+    g = inputs.sinogram(ph, G.N, G.Nz, G.Ns, G.Ntheta, G.Npi, noise=0.01, seed=1).numpy()
+    _, r0 = O.solve(og(G), g, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=9)
+    return G, g, r0
+
+
+@pytest.mark.parametrize("variant", ["plain", "accel"])
+def test_uniformly_convex_solve_c1(variant):
+    """The model with the uniformly convex term mu/2 |f|^2 (mu = 1e-3 L_R^2),
+    plain and accelerated loops (adaptive theta, tau, sigma): 60 iterations
+    of the C1 workload against the oracle's, iterate within 1e-3, the
+    objective (with the mu term) within 1e-4, and the report's steps are the
+    initial ones."""
+    G, g, r0 = c1_problem()
+    L = r0["L_R"]
+    kw = dict(lambda1=2.0 ** -9 * L * L, lambda2=4.0, n_iter=60, tau=r0["tau"], sigma=r0["sigma"],
+              mu=1e-3 * L * L, variant=variant)
+    p = rt4d.Plan(G)
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = p.solve(T(g), f, **kw)
+    fo, ro = O.solve(og(G), g, route="folded", **kw)
+    print(f"{variant}: objective {rep['objective']:.9e} vs {ro['objective']:.9e}")
+    close(f.cpu().numpy(), fo, 1e-3, f"mu > 0, {variant} iterate")
+    assert abs(rep["objective"] - ro["objective"]) <= 1e-4 * abs(ro["objective"])
+    assert rep["tau"] == r0["tau"] and rep["sigma"] == r0["sigma"]
+
+
+def test_accelerated_checkpoint_resume_bitwise():
+    """The accelerated loop's adapted steps survive a checkpoint: 20 + 20
+    iterations through a restored job equal 40 in one go, bit for bit."""
+    G = SHAPES[1]
+    p = rt4d.Plan(G)
+    g0 = inputs.uniform(G.g_shape, 33)
+    g = T(g0)
+    st = safe_steps(G, g0, 2.0)
+    kw = dict(lambda1=0.1, lambda2=2.0, n_iter=40, tau=st, sigma=st, mu=0.5, variant="accel")
+    fa = torch.zeros(G.f_shape, device=DEV)
+    ja = rt4d.Job(p, g, fa, **kw)
+    ja.step(40)
+    fb = torch.zeros(G.f_shape, device=DEV)
+    jb = rt4d.Job(p, g, fb, **kw)
+    jb.step(20)
+    ck = jb.checkpoint()
+    jb.close()
+    fc = torch.zeros(G.f_shape, device=DEV)
+    jc = rt4d.Job(p, g, fc, **kw)
+    jc.restore(ck)
+    jc.step(40)
+    torch.cuda.synchronize()
+    assert jc.iters == 40 and torch.equal(fa, fc)
+    assert ja.report() == jc.report()
 
 
 def test_step_rule_power_iteration():
@@ -264,10 +332,9 @@ def test_precision_form_parity(G):
         f = inputs.uniform(G.f_shape, seed) if maker == "uniform" else \
             inputs.smooth_coeffs(G.N, G.Nz, G.K, seed)
         s = inputs.uniform(G.g_shape, seed + 100)
-        e_f = rel(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f))
-        e_a = rel(p.adjoint(T(s)).cpu().numpy(), O.adjoint(og(G), s))
-        print(f"case {G} {maker}: precision forward {e_f:.2e} adjoint {e_a:.2e}")
-        assert e_f <= 3e-3 and e_a <= 3e-3
+        print(f"case {G} {maker}", flush=True)
+        close(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f), 3e-3, "precision forward")
+        close(p.adjoint(T(s)).cpu().numpy(), O.adjoint(og(G), s), 3e-3, "precision adjoint")
 
 
 def test_precision_form_line_parts():
@@ -279,20 +346,15 @@ def test_precision_form_line_parts():
     G = rt4d.Geom(N=2048, Nz=2, Ns=64, Ntheta=2 * 4, Npi=2, K=32, Nt=2)
     p = rt4d.Plan(G, form=rt4d.RT_FORM_SF, prec=rt4d.RT_PREC_BF16MFMA)
     f = inputs.uniform(G.f_shape, 43)
-    e_f = rel(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f))
-    print(f"line parts: precision forward {e_f:.2e}", flush=True)
-    assert e_f <= 3e-3
-    g = T(inputs.uniform(G.g_shape, 44, 0.0, 1.0))
+    close(p.forward(T(f)).cpu().numpy(), O.forward(og(G), f), 3e-3, "line parts: precision forward")
+    g0 = inputs.uniform(G.g_shape, 44, 0.0, 1.0)
     kw = dict(lambda1=0.5, lambda2=1.0, n_iter=3, tau=1e-4, sigma=1e-4, check_every=1)
     f_sf = torch.zeros(G.f_shape, device=DEV)
-    r_sf = p.solve(g, f_sf, **kw)
-    f_pf = torch.zeros(G.f_shape, device=DEV)
-    r_pf = rt4d.Plan(G).solve(g, f_pf, **kw)
-    d = float(torch.linalg.vector_norm((f_sf - f_pf).double()) / torch.linalg.vector_norm(f_pf.double()))
-    print(f"line parts: solve f rel {d:.2e}, residual {r_sf['residual']:.6e} vs {r_pf['residual']:.6e}",
-          flush=True)
-    assert d <= 3e-3
-    assert abs(r_sf["residual"] - r_pf["residual"]) <= 3e-3 * r_pf["residual"]
+    r_sf = p.solve(T(g0), f_sf, **kw)
+    fo, ro = O.solve(og(G), g0, route="folded", **kw)
+    close(f_sf.cpu().numpy(), fo, 1e-3, "line parts: precision solve iterate")
+    print(f"line parts: residual {r_sf['residual']:.9e} vs {ro['residual']:.9e}", flush=True)
+    assert abs(r_sf["residual"] - ro["residual"]) <= 3e-3 * ro["residual"]
 
 
 def test_precision_form_solve_c1():
@@ -307,10 +369,9 @@ def test_precision_form_solve_c1():
     f = torch.zeros(G.f_shape, device=DEV)
     rep = p.solve(T(g), f, **kw)
     fo, ro = O.solve(og(G), g, route="folded", **kw)
-    e = rel(f.cpu().numpy(), fo)
-    print(f"precision-form C1 solve rel {e:.2e}; objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
-    assert e <= 1e-2
-    assert abs(rep["objective"] - ro["objective"]) <= 1e-2 * abs(ro["objective"])
+    print(f"precision-form C1 solve: objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
+    close(f.cpu().numpy(), fo, 1e-3, "precision-form C1 solve iterate")
+    assert abs(rep["objective"] - ro["objective"]) <= 1e-3 * abs(ro["objective"])
 
 
 def test_precision_form_deterministic():
