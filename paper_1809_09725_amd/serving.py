@@ -17,7 +17,13 @@ fixed number of iterations through the rt_job API of librt4d.  The loop
     busy; the device has no notion of priority, so the host does the
     ordering by what it queues;
   * runs the setup of a job (plan tables, power iteration for the step size)
-    on a worker thread, so that admission never stalls the issue loop.
+    on a worker thread, so that admission never stalls the issue loop;
+  * isolates failures: a job larger than the whole budget is rejected on its
+    own, a job whose setup or iteration raises (a non-finite sinogram found
+    by the FP64 finiteness check at admission, a library error, a device
+    allocation failure) is marked failed and its memory freed, and a job can
+    be cancelled while waiting, in setup or running; every other job goes on
+    as if that job had never been there.
 
 The same loop drives a fake device in the CPU tests (`FakeBackend`), which
 checks the admission, ordering and accounting logic without a GPU.
@@ -28,6 +34,7 @@ one job at a time in arrival order.
 from __future__ import annotations
 
 import math
+import threading
 import time
 from collections import deque
 from concurrent.futures import ThreadPoolExecutor
@@ -53,6 +60,7 @@ class JobSpec:
     seed: int
     lambda1: float
     lambda2: float = 4.0
+    cancel_at: float = math.inf   # the client withdraws the request at this time
 
     @property
     def Ns(self) -> int:
@@ -114,6 +122,8 @@ class Record:
     bytes: int = 0
     iters: int = 0
     report: dict = field(default_factory=dict)
+    status: str = "pending"   # done | failed | rejected | cancelled
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -121,12 +131,18 @@ class Record:
 
 
 def summarize(records: list[Record], makespan: float) -> dict:
-    lat = np.array([r.latency for r in records])
-    return {"jobs": len(records), "makespan_s": makespan,
-            "jobs_per_hour": 3600.0 * len(records) / makespan if makespan > 0 else math.inf,
-            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
-            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
-            "mean_latency_s": float(lat.mean()) if len(lat) else math.nan}
+    """Throughput and latency over the jobs that completed; the others are
+    counted by status."""
+    ok = [r for r in records if r.status == "done"]
+    lat = np.array([r.latency for r in ok])
+    out = {"jobs": len(ok), "makespan_s": makespan,
+           "jobs_per_hour": 3600.0 * len(ok) / makespan if makespan > 0 else math.inf,
+           "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+           "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+           "mean_latency_s": float(lat.mean()) if len(lat) else math.nan}
+    for st in ("failed", "rejected", "cancelled"):
+        out[st] = sum(r.status == st for r in records)
+    return out
 
 
 # --------------------------------------------------------------------------- scheduler
@@ -158,13 +174,22 @@ class Scheduler:
         self.log = log           # called with a line per finished job
         self.starve_s = starve_s
         self.form = form         # for the work estimate of each job
+        self._cancel: set[int] = set()
+        self._cancel_lock = threading.Lock()
+
+    def cancel(self, jid: int) -> None:
+        """Withdraw job `jid` (safe from any thread): a waiting job leaves the
+        queue, a job in setup is released when its setup ends, a running job
+        is released at once (its queued iterations drain first)."""
+        with self._cancel_lock:
+            self._cancel.add(jid)
+
+    def _cancelled(self, jid: int) -> bool:
+        with self._cancel_lock:
+            return jid in self._cancel
 
     def run(self, trace: list[JobSpec]) -> tuple[list[Record], dict]:
         be = self.be
-        for s in trace:
-            if be.bytes_needed(s) > self.budget:
-                raise ValueError(f"job {s.jid} needs {be.bytes_needed(s)} bytes, more than the "
-                                 f"whole budget {self.budget}")
         future = deque(sorted(trace, key=lambda s: (s.arrival, s.jid)))
         waiting: deque[JobSpec] = deque()
         setting_up: list[_Active] = []
@@ -173,12 +198,46 @@ class Scheduler:
         used = 0
         max_resident = 0
         t0 = be.now()
+
+        def close(a: _Active, status: str, err: str = "") -> None:
+            nonlocal used
+            a.rec.status, a.rec.error = status, err
+            a.rec.iters = a.done
+            a.rec.finished = be.now() - t0
+            try:
+                be.release(a.h)
+            except Exception as e:      # the memory is the backend's to reclaim; keep serving
+                a.rec.error += f"; release: {e}"
+            used -= a.rec.bytes
+            if self.log:
+                s = a.spec
+                self.log(f"served job {s.jid} (N={s.N} Nz={s.Nz} K={s.K}) {status} at "
+                         f"{a.rec.finished:.1f} s{': ' + err if err else ''}")
+
         while future or waiting or setting_up or active:
             now = be.now() - t0
             while future and future[0].arrival <= now:
                 s = future.popleft()
+                rec = records[s.jid] = Record(jid=s.jid, arrival=s.arrival)
+                need = be.bytes_needed(s)
+                if need > self.budget:
+                    rec.status, rec.finished = "rejected", now
+                    rec.error = f"needs {need} bytes, more than the whole budget {self.budget}"
+                    if self.log:
+                        self.log(f"job {s.jid} rejected: {rec.error}")
+                    continue
                 waiting.append(s)
-                records[s.jid] = Record(jid=s.jid, arrival=s.arrival)
+            # ---- cancellations (client requests and the trace's own)
+            for s in list(waiting):
+                if s.cancel_at <= now or self._cancelled(s.jid):
+                    waiting.remove(s)
+                    r = records[s.jid]
+                    r.status, r.finished = "cancelled", now
+            for a in list(active):
+                if a.spec.cancel_at <= now or self._cancelled(a.spec.jid):
+                    active.remove(a)
+                    a.done = be.completed(a.h)
+                    close(a, "cancelled")
             # ---- admission: oldest first, back-fill while the oldest is not starving
             n_res = len(active) + len(setting_up)
             i = 0
@@ -198,39 +257,50 @@ class Scheduler:
                     break          # reserve freed memory for the oldest job
                 i += 1
             max_resident = max(max_resident, len(active) + len(setting_up))
-            # ---- jobs whose setup finished join the active set
+            # ---- jobs whose setup finished join the active set (or fail alone)
             for a in list(setting_up):
-                if be.ready(a.h):
+                try:
+                    ok = be.ready(a.h)
+                except Exception as e:
+                    setting_up.remove(a)
+                    close(a, "failed", f"setup: {e}")
+                    continue
+                if ok:
                     setting_up.remove(a)
                     a.rec.ready = be.now() - t0
-                    active.append(a)
+                    if a.spec.cancel_at <= be.now() - t0 or self._cancelled(a.spec.jid):
+                        close(a, "cancelled")
+                    else:
+                        active.append(a)
             # ---- completions
             for a in list(active):
-                a.done = be.completed(a.h)
-                if a.done >= a.spec.n_iter:
+                try:
+                    a.done = be.completed(a.h)
+                    if a.done < a.spec.n_iter:
+                        continue
                     a.rec.report = be.finish(a.h)
-                    a.rec.iters = a.done
-                    a.rec.finished = be.now() - t0
-                    be.release(a.h)
-                    used -= a.rec.bytes
+                except Exception as e:
                     active.remove(a)
-                    if self.log:
-                        s = a.spec
-                        self.log(f"served job {s.jid} (N={s.N} Nz={s.Nz} K={s.K}) done at "
-                                 f"{a.rec.finished:.1f} s, latency {a.rec.latency:.1f} s, "
-                                 f"{len(active)} active, {len(waiting)} waiting")
+                    close(a, "failed", f"iteration {a.done}: {e}")
+                    continue
+                active.remove(a)
+                close(a, "done")
             # ---- issue: the `window` jobs with least remaining work, `depth` queued each
             issued = False
             order = sorted(active, key=lambda a: (a.remaining(), a.spec.jid))
             for a in order[:self.window]:
-                while a.issued < a.spec.n_iter and a.issued - a.done < self.depth:
-                    be.issue(a.h)
-                    a.issued += 1
-                    issued = True
+                try:
+                    while a.issued < a.spec.n_iter and a.issued - a.done < self.depth:
+                        be.issue(a.h)
+                        a.issued += 1
+                        issued = True
+                except Exception as e:
+                    active.remove(a)
+                    close(a, "failed", f"issue of iteration {a.issued + 1}: {e}")
             if not issued:
                 nxt = future[0].arrival - (be.now() - t0) if future else None
                 be.wait(nxt)
-        makespan = max((r.finished for r in records.values()), default=0.0)
+        makespan = max((r.finished for r in records.values() if r.status == "done"), default=0.0)
         recs = [records[s.jid] for s in trace]
         st = summarize(recs, makespan)
         st["max_resident"] = max_resident
@@ -306,6 +376,13 @@ class GpuBackend:
         with torch.cuda.stream(sl.stream):
             host = self.payload(s)
             sl.g = host.to(self.dev, non_blocking=True)
+            if tuple(sl.g.shape) != tuple(G.g_shape) or sl.g.dtype != torch.float32:
+                raise ValueError(f"sinogram of shape {tuple(sl.g.shape)} ({sl.g.dtype}), expected "
+                                 f"{tuple(G.g_shape)} float32")
+            # admission check: sum g^2 in FP64 on the device is finite exactly
+            # when every sample is (the iteration has no monitor to notice)
+            if not math.isfinite(rt.rt_dot(sl.g.view(-1), sl.g.view(-1))):
+                raise ValueError("non-finite sinogram")
             sl.f = torch.zeros(G.f_shape, device=self.dev)
             form, prec = self._form(s)
             sl.plan = rt.Plan(G, form=form, prec=prec)
@@ -346,10 +423,18 @@ class GpuBackend:
         return rep
 
     def release(self, sl: _Slot) -> None:
-        sl.job.close()
-        sl.plan.close()
+        """Free the job's device state; works on a slot whose setup failed
+        part way (whatever was created is closed)."""
+        if sl.future is not None and not sl.future.done():
+            sl.future.exception()          # wait for the setup thread to let go
+        sl.stream.synchronize()
+        if sl.job is not None:
+            sl.job.close()
+        if sl.plan is not None:
+            sl.plan.close()
         sl.g = sl.f = None
         sl.job = sl.plan = None
+        sl.events.clear()
 
     def wait(self, until_next_arrival) -> None:
         dt = self.poll_s if until_next_arrival is None else min(self.poll_s, max(0.0, until_next_arrival))
@@ -388,6 +473,7 @@ def serial_baseline(trace: list[JobSpec], payload, device: int = 0, n_pow: int =
         torch.cuda.synchronize(dev)
         rec.finished = time.perf_counter() - t0
         rec.iters = s.n_iter
+        rec.status = "done"
         recs.append(rec)
         if log:
             log(f"plain job {s.jid} (N={s.N} Nz={s.Nz} K={s.K}) done at {rec.finished:.1f} s, "
@@ -408,8 +494,11 @@ class FakeBackend:
     `overlap` when several jobs are queued (a crude model of small jobs
     sharing the device).  Setup takes `setup_s` seconds."""
 
-    def __init__(self, cost, setup_s: float = 0.0, overlap: float = 1.0, bytes_fn=None):
+    def __init__(self, cost, setup_s: float = 0.0, overlap: float = 1.0, bytes_fn=None,
+                 fail_setup=(), fail_at=None):
         self.cost = cost
+        self.fail_setup = set(fail_setup)     # jids whose setup raises
+        self.fail_at = dict(fail_at or {})    # jid -> iteration whose issue raises
         self.setup_s = setup_s
         self.overlap = overlap
         self.bytes_fn = bytes_fn or (lambda s: s.Nz * s.N * s.N * s.K * 4 * 6)
@@ -444,10 +533,14 @@ class FakeBackend:
         if self.t >= sl.ready_at:
             if sl in self.pending:
                 self.pending.remove(sl)
+            if sl.spec.jid in self.fail_setup:
+                raise ValueError("non-finite sinogram")
             return True
         return False
 
     def issue(self, sl) -> None:
+        if self.fail_at.get(sl.spec.jid) == sl.issued + 1:
+            raise RuntimeError("simulated library error")
         sl.issued += 1
         self.queue.append(sl)
 
@@ -475,6 +568,10 @@ class FakeBackend:
 
     def release(self, sl) -> None:
         self.live_bytes -= self.bytes_needed(sl.spec)
+        if sl in self.pending:
+            self.pending.remove(sl)
+        # iterations of a released job still queued are dropped
+        self.queue = deque(q for q in self.queue if q is not sl)
 
     def wait(self, until_next_arrival) -> None:
         # advance to the next event: the head iteration's end, a setup end or an arrival

@@ -60,3 +60,32 @@ def test_serial_baseline_matches_plain_solver():
     assert fins == sorted(fins)
     for s in tr:
         assert torch.equal(res[s.jid], alone(s, "pf"))
+
+
+def test_nonfinite_job_fails_alone():
+    """A job whose sinogram holds a NaN is caught by the FP64 finiteness check
+    at admission and marked failed; every other job of the mix is bitwise the
+    same as alone (NaN here is only data: no kernel sees it)."""
+    torch.cuda.set_device(0)
+    tr = tiny_trace()
+    bad = tr[2].jid
+
+    def pay(s):
+        p = payload(s)
+        if s.jid == bad:
+            p = p.clone()
+            p[5, 0, 3] = float("nan")
+        return p
+
+    be = GpuBackend(pay, form="auto", keep_results=True)
+    recs, st = Scheduler(be, 8 << 30, max_active=4, depth=2, form="auto").run(tr)
+    be.close()
+    r = {x.jid: x for x in recs}
+    assert r[bad].status == "failed" and "non-finite" in r[bad].error, r[bad]
+    assert st["failed"] == 1 and st["jobs"] == len(tr) - 1
+    for s in tr:
+        if s.jid == bad:
+            assert s.jid not in be.results
+            continue
+        assert r[s.jid].status == "done"
+        assert torch.equal(be.results[s.jid], alone(s, pick_form(s, "auto")))

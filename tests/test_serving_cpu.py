@@ -104,13 +104,57 @@ def test_concurrency_beats_serial_when_jobs_share_the_device():
     assert served["jobs_per_hour"] > serial["jobs_per_hour"]
 
 
-def test_job_larger_than_budget_rejected():
-    s = spec(0, 0.0, N=256, Nz=32)
+def test_job_larger_than_budget_rejected_alone():
+    big = spec(0, 0.0, N=256, Nz=32)
+    small = [spec(j, 0.001 * j, N=32, Nz=1) for j in range(1, 4)]
     be = FakeBackend(cost)
-    with pytest.raises(ValueError):
-        Scheduler(be, be.bytes_needed(s) - 1).run([s])
+    recs, st = Scheduler(be, be.bytes_needed(big) - 1).run([big] + small)
+    r = {x.jid: x for x in recs}
+    assert r[0].status == "rejected" and "budget" in r[0].error and r[0].iters == 0
+    assert all(r[j].status == "done" and r[j].iters == 10 for j in (1, 2, 3))
+    assert st["jobs"] == 3 and st["rejected"] == 1 and st["failed"] == 0
+    assert 0 not in be.order and be.live_bytes == 0
     with pytest.raises(ValueError):
         Scheduler(be, 0)
+
+
+def test_failures_are_isolated():
+    """A job whose setup raises (e.g. a non-finite sinogram) and one whose
+    fourth iteration raises are marked failed and freed; the others finish
+    with exactly the iterations they would have run without them."""
+    tr = [spec(j, 0.001 * j, N=32 * (1 + j % 2), Nz=1 + j % 3) for j in range(8)]
+    be = FakeBackend(cost, setup_s=0.001, fail_setup={2}, fail_at={5: 4})
+    budget = 3 * max(be.bytes_needed(s) for s in tr)
+    recs, st = Scheduler(be, budget, max_active=4).run(tr)
+    r = {x.jid: x for x in recs}
+    assert r[2].status == "failed" and "setup" in r[2].error and r[2].iters == 0
+    assert r[5].status == "failed" and "iteration 4" in r[5].error and r[5].iters <= 3
+    for j in (0, 1, 3, 4, 6, 7):
+        assert r[j].status == "done" and r[j].iters == 10
+        assert be.order.count(j) == 10
+    assert be.order.count(2) == 0 and be.order.count(5) <= 3
+    assert st["jobs"] == 6 and st["failed"] == 2
+    assert be.live_bytes == 0 and be.peak_bytes <= budget
+    assert st["makespan_s"] == pytest.approx(max(r[j].finished for j in (0, 1, 3, 4, 6, 7)))
+
+
+def test_cancellation_while_waiting_and_while_running():
+    tr = [spec(0, 0.0, N=64, Nz=4, n_iter=40), spec(1, 0.0, N=64, Nz=4, n_iter=40),
+          spec(2, 0.0, N=32, Nz=1, n_iter=10)]
+    one_iter = cost(tr[0])
+    tr[0].cancel_at = 5.5 * one_iter         # running: withdrawn after a few iterations
+    be = FakeBackend(cost)
+    # budget for one job at a time: job 1 waits, and is cancelled from outside
+    sched = Scheduler(be, be.bytes_needed(tr[0]), max_active=4)
+    sched.cancel(1)
+    recs, st = sched.run(tr)
+    r = {x.jid: x for x in recs}
+    assert r[0].status == "cancelled" and 0 < r[0].iters < 40
+    assert r[1].status == "cancelled" and r[1].iters == 0 and be.order.count(1) == 0
+    assert r[2].status == "done" and r[2].iters == 10
+    assert st["cancelled"] == 2 and st["jobs"] == 1 and be.live_bytes == 0
+    # a cancelled job's queued iterations were dropped, not run
+    assert be.order.count(0) == r[0].iters
 
 
 def test_window_one_runs_shortest_remaining_first():
