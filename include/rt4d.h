@@ -76,8 +76,13 @@ typedef enum {
  * project-first projects the K coefficient volumes over the Ntheta0 angles
  * of [0,pi) and distributes them with the s-flip to every half-turn (Sec. 4,
  * eq. radapr and the pi-periodicity); synthesise-first forms the states
- * sum_k Phi[i][k] f_k and projects those. */
-typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1 } rt_form;
+ * sum_k Phi[i][k] f_k and projects those.  RT_FORM_AUTO lets the library
+ * choose (rt_form_pick): project-first taps K channels per ray and line,
+ * synthesise-first taps Npi frames (rounded up to 4) and also forms them, so
+ * with RT_PREC_BF16MFMA it takes synthesise-first when K >= 2 Npi and
+ * Npi <= 32, and project-first in FP32 otherwise; with RT_PREC_FP32 it is
+ * project-first. */
+typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1, RT_FORM_AUTO = 2 } rt_form;
 
 /* RT_PREC_FP32: every product in FP32.  RT_PREC_BF16MFMA: the basis
  * contraction sum_k Phi f_k (and its transpose) in BF16 on the matrix cores
@@ -101,6 +106,31 @@ void rt_plan_destroy(rt_plan *plan);
 
 /* Device bytes the plan holds (tables + scratch). */
 int rt_plan_bytes(const rt_plan *plan, size_t *bytes);
+
+/* The form and precision a plan of this geometry runs for the requested
+ * pair: RT_FORM_AUTO resolved as stated at rt_form, the other forms checked
+ * and returned as they are (RT_E_ARG / RT_E_SHAPE as rt_plan_create would
+ * give).  Host only; the outputs may not be NULL. */
+int rt_form_pick(const rt_geom *geom, rt_form form, rt_prec prec, rt_form *form_out,
+                 rt_prec *prec_out);
+
+/* The form and precision the plan runs (never RT_FORM_AUTO).  Host only. */
+int rt_plan_form(const rt_plan *plan, rt_form *form, rt_prec *prec);
+
+/* Tables of the paper's Fourier basis of M functions (Sec. 5:
+ * phi_j(t) = exp(2 pi i t (j - M/2)), j = 0 .. M-1; Sec. 6 takes M = 16) in
+ * the real form that spans the same real-valued objects: a real f(t) has
+ * coefficients with c_{-v} = conj(c_v), and the lone frequency -M/2 carries
+ * no real function, so the span is the K = M - 1 functions
+ *   1, cos(2 pi v t), sin(2 pi v t)   for v = 1 .. M/2 - 1, in that order.
+ * Real coefficients (a_0, a_v, b_v) and the complex ones are related by
+ * c_0 = a_0, c_v = (a_v - i b_v) / 2, c_{-v} = (a_v + i b_v) / 2,
+ * c_{-M/2} = 0; the adjoint's conj(phi) (Sec. 4) is the transpose of this
+ * real table.  Fills host FP64 phi[Ntheta][K] at t_i = i/Ntheta and
+ * S[Nt][K] at the half-turn starts (t = m Ntheta0 / Ntheta), for
+ * rt_plan_create.  M even, M >= 2, and geom->K == M - 1 (RT_E_ARG else).
+ * Host only. */
+int rt_basis_fourier(const rt_geom *geom, int32_t M, double *phi, double *S);
 
 /* Copy the host tables (Sec. 4, eq. discrt): theta[Ntheta] = i*pi/Ntheta0,
  * t[Ntheta] = i/Ntheta, cls[Ntheta] = i mod Ntheta0, rot[Ntheta] =
@@ -259,6 +289,16 @@ int rt_dot(const float *x, const float *y, size_t n, double *out, void *stream);
 int rt_timing_enable(int on);
 int rt_timing_reset(void);
 int rt_timing_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* ---- measurement aid -----------------------------------------------------
+ * The FP32 fused multiply-add issue rate of the device: n_blocks workgroups
+ * of 256 threads, each thread 8 independent chains of 16 * n_iter unpacked
+ * FMAs, no memory traffic inside the loop.  out: device float[n_blocks * 256]
+ * (one value per thread, to keep the chains live).  *ms = elapsed time of the
+ * launch between two events on `stream`; *flop = 2 * 8 * 16 * n_iter * 256 *
+ * n_blocks.  Blocks until the kernel is done.  Not part of the method. */
+int rt_calib_fma(int32_t n_blocks, int32_t n_iter, float *out, double *ms, double *flop,
+                 void *stream);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *rt_last_error(void);

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "abi.cpp", "solve.cpp", "timing.cpp", "proj_pf.hip", "backproject.hip", "proj_sf.hip", "tv.hip",
-           "reduce.hip", "fbp.hip", "ooc.cpp"]
+           "reduce.hip", "fbp.hip", "ooc.cpp", "calib.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,

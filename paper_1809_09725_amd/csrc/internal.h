@@ -165,6 +165,8 @@ int launch_fbp_filter(const Plan &p, const float *g, float *q, hipStream_t s);
 int fbp_init(const Plan &p, const float *g, float *f, hipStream_t s);
 
 int check_geom(const rt_geom *g);
+// checks the form and precision and resolves RT_FORM_AUTO (in place)
+int pick_form(const rt_geom *geom, rt_form *form, rt_prec *prec);
 int check_plan(const rt_plan *p);
 
 // ---------------------------------------------------------------- launchers

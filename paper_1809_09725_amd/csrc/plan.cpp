@@ -357,26 +357,87 @@ static int create(const rt_geom *geom, rt_form form, rt_prec prec, const double 
     return RT_OK;
 }
 
+int pick_form(const rt_geom *geom, rt_form *form, rt_prec *prec)
+{
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (*form != RT_FORM_PF && *form != RT_FORM_SF && *form != RT_FORM_AUTO)
+        return fail(RT_E_ARG, "unknown form %d", (int)*form);
+    if (*prec != RT_PREC_FP32 && *prec != RT_PREC_BF16MFMA)
+        return fail(RT_E_ARG, "unknown precision %d", (int)*prec);
+    if (*form == RT_FORM_AUTO) {
+        // per ray and line, project-first taps K channels; synthesise-first
+        // taps the Npi frames (rounded up to 4) and forms them on the matrix
+        // cores, which pays from about K = 2 Npi (measured per iteration at
+        // 8 half-turns: SF/PF 0.53-0.95 at K = 32, 0.97-1.08 at K = 16,
+        // 1.2-1.7 at K = 8; 1.24 at K = 16 over 12 half-turns)
+        const bool sf = *prec == RT_PREC_BF16MFMA && geom->K >= 2 * geom->Npi && geom->Npi <= 32;
+        *form = sf ? RT_FORM_SF : RT_FORM_PF;
+        *prec = sf ? RT_PREC_BF16MFMA : RT_PREC_FP32;
+        return RT_OK;
+    }
+    if (*prec == RT_PREC_BF16MFMA && *form != RT_FORM_SF)
+        return fail(RT_E_ARG, "the BF16 contraction needs the synthesise-first form");
+    if (*form == RT_FORM_SF && *prec != RT_PREC_BF16MFMA)
+        return fail(RT_E_ARG, "the synthesise-first form is built with the BF16 contraction only");
+    if (*form == RT_FORM_SF && geom->Npi > 32)
+        return fail(RT_E_SHAPE, "the synthesise-first form needs Npi <= 32 (got %d)", geom->Npi);
+    return RT_OK;
+}
+
 }  // namespace rt
 
 using namespace rt;
+
+extern "C" int rt_form_pick(const rt_geom *geom, rt_form form, rt_prec prec, rt_form *form_out,
+                            rt_prec *prec_out)
+{
+    if (!form_out || !prec_out) return fail(RT_E_ARG, "NULL output");
+    int rc = pick_form(geom, &form, &prec);
+    if (rc) return rc;
+    *form_out = form;
+    *prec_out = prec;
+    return RT_OK;
+}
+
+extern "C" int rt_basis_fourier(const rt_geom *geom, int32_t M, double *phi, double *S)
+{
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!phi || !S) return fail(RT_E_ARG, "NULL table");
+    if (M < 2 || M % 2 || geom->K != M - 1)
+        return fail(RT_E_ARG, "the real form of M = %d Fourier functions has K = M - 1 (got K = %d)",
+                    (int)M, geom->K);
+    const int K = geom->K, n0 = geom->Ntheta / geom->Npi;
+    auto row = [&](double t, double *out) {
+        out[0] = 1.0;
+        for (int v = 1; v <= M / 2 - 1; ++v) {
+            const double w = 2.0 * M_PI * (double)v * t;
+            out[2 * v - 1] = std::cos(w);
+            out[2 * v] = std::sin(w);
+        }
+    };
+    for (int i = 0; i < geom->Ntheta; ++i) row((double)i / (double)geom->Ntheta, phi + (size_t)i * K);
+    for (int m = 0; m < geom->Nt; ++m)
+        row((double)(m * n0) / (double)geom->Ntheta, S + (size_t)m * K);
+    return RT_OK;
+}
+
+extern "C" int rt_plan_form(const rt_plan *p, rt_form *form, rt_prec *prec)
+{
+    if (check_plan(p) || !form || !prec) return fail(RT_E_ARG, "NULL argument");
+    *form = p->impl.form;
+    *prec = p->impl.prec;
+    return RT_OK;
+}
 
 extern "C" int rt_plan_create(const rt_geom *geom, rt_form form, rt_prec prec, const double *phi,
                               const double *S, rt_plan **out)
 {
     if (!out) return fail(RT_E_ARG, "out is NULL");
     *out = nullptr;
-    int rc = check_geom(geom);
+    int rc = pick_form(geom, &form, &prec);
     if (rc) return rc;
-    if (form != RT_FORM_PF && form != RT_FORM_SF) return fail(RT_E_ARG, "unknown form %d", (int)form);
-    if (prec != RT_PREC_FP32 && prec != RT_PREC_BF16MFMA)
-        return fail(RT_E_ARG, "unknown precision %d", (int)prec);
-    if (prec == RT_PREC_BF16MFMA && form != RT_FORM_SF)
-        return fail(RT_E_ARG, "the BF16 contraction needs the synthesise-first form");
-    if (form == RT_FORM_SF && prec != RT_PREC_BF16MFMA)
-        return fail(RT_E_ARG, "the synthesise-first form is built with the BF16 contraction only");
-    if (form == RT_FORM_SF && geom->Npi > 32)
-        return fail(RT_E_SHAPE, "the synthesise-first form needs Npi <= 32 (got %d)", geom->Npi);
     if (phi)
         for (size_t e = 0; e < (size_t)geom->Ntheta * geom->K; ++e)
             if (!std::isfinite(phi[e])) return fail(RT_E_ARG, "phi has a non-finite entry");

@@ -306,9 +306,9 @@ double cp_steps(const rt_solve_params &P, double *tau, double *sigma, double *ci
 }
 }  // namespace rt
 
-extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec, size_t *bytes)
+extern "C" int rt_job_bytes(const rt_geom *geom, rt_form form, rt_prec prec, size_t *bytes)
 {
-    int rc = check_geom(geom);
+    int rc = pick_form(geom, &form, &prec);
     if (rc) return rc;
     if (!bytes) return fail(RT_E_ARG, "bytes is NULL");
     const rt_geom &g = *geom;

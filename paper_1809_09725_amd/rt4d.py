@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librt4d.so")
 
 RT_OK, RT_E_ARG, RT_E_SHAPE, RT_E_HIP, RT_E_OOM, RT_E_NONFINITE = 0, -1, -2, -3, -4, -5
-RT_FORM_PF, RT_FORM_SF = 0, 1
+RT_FORM_PF, RT_FORM_SF, RT_FORM_AUTO = 0, 1, 2
 RT_PREC_FP32, RT_PREC_BF16MFMA = 0, 1
 RT_CP_PLAIN, RT_CP_ACCEL = 0, 1
 
@@ -31,7 +31,7 @@ EXPORTS = ("rt_plan_create", "rt_plan_destroy", "rt_plan_bytes", "rt_tables", "r
            "rt_job_create", "rt_job_step", "rt_job_done", "rt_job_iters", "rt_job_report",
            "rt_job_checkpoint_bytes", "rt_job_checkpoint", "rt_job_restore", "rt_job_destroy",
            "rt_dot", "rt_timing_enable", "rt_timing_reset", "rt_timing_read", "rt_last_error",
-           "rt_fbp_filter", "rt_fbp", "rt_solve_ooc")
+           "rt_fbp_filter", "rt_fbp", "rt_solve_ooc", "rt_calib_fma", "rt_form_pick", "rt_plan_form", "rt_basis_fourier")
 
 
 class RtError(RuntimeError):
@@ -102,6 +102,10 @@ def lib() -> ctypes.CDLL:
         "rt_fbp": (c_int, [vp, vp, vp, vp]),
         "rt_solve_ooc": (c_int, [P(rt_geom), vp, vp, P(rt_solve_params), vp, vp, i32,
                                  P(rt_solve_report), vp]),
+        "rt_form_pick": (c_int, [P(rt_geom), c_int, c_int, P(c_int), P(c_int)]),
+        "rt_plan_form": (c_int, [vp, P(c_int), P(c_int)]),
+        "rt_basis_fourier": (c_int, [P(rt_geom), i32, vp, vp]),
+        "rt_calib_fma": (c_int, [i32, i32, vp, P(ctypes.c_double), P(ctypes.c_double), vp]),
         "rt_timing_enable": (c_int, [c_int]),
         "rt_timing_reset": (c_int, []),
         "rt_timing_read": (c_int, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
@@ -281,6 +285,42 @@ def solve(plan: "Plan", params: rt_solve_params, g: torch.Tensor, f: torch.Tenso
     return rep.as_dict()
 
 
+def form_pick(geom: Geom, form: int = RT_FORM_AUTO, prec: int = RT_PREC_BF16MFMA) -> tuple[int, int]:
+    """(form, precision) a plan of this geometry runs for the requested pair;
+    RT_FORM_AUTO is resolved by the library's rule.  Host only."""
+    fo, po = ctypes.c_int(), ctypes.c_int()
+    _check(lib().rt_form_pick(ctypes.byref(geom.c()), form, prec, ctypes.byref(fo), ctypes.byref(po)))
+    return fo.value, po.value
+
+
+def basis_fourier(geom: Geom, M: int):
+    """(phi [Ntheta][K], S [Nt][K]) FP64 host tables of the real form of the
+    paper's Fourier basis of M functions (K = M - 1), for Plan(phi=, S=)."""
+    import numpy as np
+    phi = np.empty((geom.Ntheta, geom.K), np.float64)
+    S = np.empty((geom.Nt, geom.K), np.float64)
+    _check(lib().rt_basis_fourier(ctypes.byref(geom.c()), M, ctypes.c_void_p(phi.ctypes.data),
+                                  ctypes.c_void_p(S.ctypes.data)))
+    return phi, S
+
+
+def fourier_complex_coeffs(f_real: torch.Tensor, M: int) -> torch.Tensor:
+    """Complex coefficients c_j, j = 0 .. M-1 (frequency j - M/2), of the
+    paper's basis from the real-form coefficients [..., K = M - 1] (last
+    axis): c_0 = a_0, c_v = (a_v - i b_v)/2, c_{-v} = (a_v + i b_v)/2,
+    c_{-M/2} = 0."""
+    K = f_real.shape[-1]
+    if K != M - 1:
+        raise ValueError(f"K = {K} real coefficients are the span of M = K + 1 functions")
+    c = torch.zeros(*f_real.shape[:-1], M, dtype=torch.complex64, device=f_real.device)
+    c[..., M // 2] = f_real[..., 0]
+    for v in range(1, M // 2):
+        a, b = f_real[..., 2 * v - 1], f_real[..., 2 * v]
+        c[..., M // 2 + v] = torch.complex(a, -b) / 2
+        c[..., M // 2 - v] = torch.complex(a, b) / 2
+    return c
+
+
 def rt_job_bytes(geom: Geom, form: int = RT_FORM_PF, prec: int = RT_PREC_FP32) -> int:
     b = ctypes.c_size_t()
     _check(lib().rt_job_bytes(ctypes.byref(geom.c()), form, prec, ctypes.byref(b)))
@@ -296,6 +336,17 @@ def rt_dot(x: torch.Tensor, y: torch.Tensor) -> float:
     _check(lib().rt_dot(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
                         ctypes.byref(out), _stream(x.device)))
     return out.value
+
+
+def calib_fma(n_blocks: int, n_iter: int, out: torch.Tensor) -> tuple[float, float]:
+    """(milliseconds, flops) of the FP32 FMA issue-rate kernel; out holds
+    n_blocks * 256 float32 values on the device."""
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < 256 * n_blocks:
+        raise ValueError("calib_fma needs a contiguous float32 tensor of n_blocks * 256 values")
+    ms, fl = ctypes.c_double(), ctypes.c_double()
+    _check(lib().rt_calib_fma(n_blocks, n_iter, ctypes.c_void_p(out.data_ptr()), ctypes.byref(ms),
+                              ctypes.byref(fl), _stream(out.device)))
+    return ms.value, fl.value
 
 
 def timing_enable(on: bool = True) -> None:
@@ -326,6 +377,9 @@ class Plan:
                                    else torch.device(device).index or 0)
         with torch.cuda.device(self.device):
             self.h = rt_plan_create(geom, form, prec, phi, S)
+        fo, po = ctypes.c_int(), ctypes.c_int()
+        _check(lib().rt_plan_form(self.h, ctypes.byref(fo), ctypes.byref(po)))
+        self.form, self.prec = fo.value, po.value   # RT_FORM_AUTO resolved by the library
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -320,14 +320,14 @@ class _Slot:
 
 
 def pick_form(s: JobSpec, form: str) -> str:
-    """'sf' or 'pf' for one job.  'auto' takes the synthesise-first precision
-    form when K >= 2 Npi: per ray and line it taps Npi frames (plus writing
-    the frames once) where project-first taps K channels, and its frame
-    synthesis costs the rest.  Measured per iteration at Npi = 8, SF / PF is
-    0.53-0.95 for K = 32, 0.97-1.08 for K = 16 and 1.2-1.7 for K = 8; with
-    K = 16, Npi = 12 (1024^2 x 64) it is 1.24."""
+    """'sf' or 'pf' for one job.  'auto' asks the library (rt_form_pick with
+    RT_FORM_AUTO and the BF16 contraction allowed): the synthesise-first
+    precision form when K >= 2 Npi and Npi <= 32, the plain FP32 form
+    otherwise."""
     if form == "auto":
-        return "sf" if s.K >= 2 * s.Npi else "pf"
+        from . import rt4d
+        fo, _ = rt4d.form_pick(s.geom(), rt4d.RT_FORM_AUTO, rt4d.RT_PREC_BF16MFMA)
+        return "sf" if fo == rt4d.RT_FORM_SF else "pf"
     return form
 
 

@@ -130,3 +130,67 @@ def test_ooc_rejects_bad_arguments_before_any_launch():
     empty = rt4d.Geom(N=16, Nz=0, Ns=16, Ntheta=24, Npi=8, K=8, Nt=8)
     assert L.rt_solve_ooc(ctypes.byref(empty.c()), None, None, ctypes.byref(prm), None, None, 2,
                           ctypes.byref(rep), None) == rt4d.RT_OK
+
+
+# ------------------------------------------------ form choice and Fourier basis (host only)
+
+@pytest.mark.parametrize("K,Npi,prec,want", [
+    (16, 8, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_SF),    # K >= 2 Npi
+    (32, 8, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_SF),
+    (15, 8, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_PF),    # K < 2 Npi
+    (16, 12, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_PF),
+    (64, 32, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_SF),
+    (64, 33, rt4d.RT_PREC_BF16MFMA, rt4d.RT_FORM_PF),   # synthesise-first needs Npi <= 32
+    (32, 8, rt4d.RT_PREC_FP32, rt4d.RT_FORM_PF),        # FP32: project-first only
+])
+def test_auto_form_rule(K, Npi, prec, want):
+    G = rt4d.Geom(N=32, Nz=1, Ns=32, Ntheta=Npi * 4, Npi=Npi, K=K, Nt=1)
+    fo, po = rt4d.form_pick(G, rt4d.RT_FORM_AUTO, prec)
+    assert fo == want
+    assert po == (rt4d.RT_PREC_BF16MFMA if want == rt4d.RT_FORM_SF else rt4d.RT_PREC_FP32)
+    # explicit forms are checked, not changed
+    assert rt4d.form_pick(G, rt4d.RT_FORM_PF, rt4d.RT_PREC_FP32) == (rt4d.RT_FORM_PF, rt4d.RT_PREC_FP32)
+    with pytest.raises(rt4d.RtError):
+        rt4d.form_pick(G, rt4d.RT_FORM_PF, rt4d.RT_PREC_BF16MFMA)
+    with pytest.raises(rt4d.RtError):
+        rt4d.form_pick(G, 7, rt4d.RT_PREC_FP32)
+
+
+def test_auto_job_bytes_match_the_chosen_form():
+    G = rt4d.Geom(N=64, Nz=4, Ns=64, Ntheta=8 * 16, Npi=8, K=32, Nt=8)
+    assert rt4d.rt_job_bytes(G, rt4d.RT_FORM_AUTO, rt4d.RT_PREC_BF16MFMA) == \
+        rt4d.rt_job_bytes(G, rt4d.RT_FORM_SF, rt4d.RT_PREC_BF16MFMA)
+    assert rt4d.rt_job_bytes(G, rt4d.RT_FORM_AUTO, rt4d.RT_PREC_FP32) == \
+        rt4d.rt_job_bytes(G, rt4d.RT_FORM_PF, rt4d.RT_PREC_FP32)
+
+
+def test_fourier_tables_span_the_complex_basis():
+    """The real table of M = 16 functions (K = 15) against numpy's complex
+    exponentials exp(2 pi i t (j - M/2)) at t_i = i/Ntheta: every real-form
+    synthesis equals the complex synthesis with the stated coefficients, and
+    the table's columns are the real and imaginary parts."""
+    import numpy as np
+    import torch
+    M = 16
+    G = rt4d.Geom(N=8, Nz=1, Ns=8, Ntheta=130 * 3, Npi=130, K=M - 1, Nt=40)
+    phi, S = rt4d.basis_fourier(G, M)
+    t = np.arange(G.Ntheta) / G.Ntheta
+    E = np.exp(2j * np.pi * np.outer(t, np.arange(M) - M // 2))     # [Ntheta][M]
+    assert np.abs(phi[:, 0] - 1).max() == 0
+    for v in range(1, M // 2):
+        assert np.abs(phi[:, 2 * v - 1] - E[:, M // 2 + v].real).max() < 1e-13
+        assert np.abs(phi[:, 2 * v] - E[:, M // 2 + v].imag).max() < 1e-13
+    n0 = G.Ntheta // G.Npi
+    assert np.array_equal(S, phi[[m * n0 for m in range(G.Nt)]])
+    rs = np.random.default_rng(3)
+    a = rs.standard_normal((5, M - 1))
+    c = rt4d.fourier_complex_coeffs(torch.from_numpy(a.astype(np.float32)), M).numpy().astype(np.complex128)
+    assert np.all(c[:, 0] == 0)                                        # frequency -M/2
+    real_form = a.astype(np.float32).astype(np.float64) @ phi.T
+    complex_form = c @ E.T
+    assert np.abs(complex_form.imag).max() < 1e-6 * np.abs(complex_form).max()
+    assert np.abs(complex_form.real - real_form).max() < 1e-6 * np.abs(real_form).max()
+    with pytest.raises(rt4d.RtError):
+        rt4d.basis_fourier(rt4d.Geom(N=8, Nz=1, Ns=8, Ntheta=16, Npi=4, K=15, Nt=4), 15)
+    with pytest.raises(rt4d.RtError):
+        rt4d.basis_fourier(rt4d.Geom(N=8, Nz=1, Ns=8, Ntheta=16, Npi=4, K=14, Nt=4), 16)

@@ -83,3 +83,47 @@ def test_fourier_basis_solve_parity():
     print(f"Fourier-basis solve rel {e:.2e}")
     assert e <= 1e-3
     assert abs(rep["objective"] - ro["objective"]) <= 1e-4 * abs(ro["objective"])
+
+
+def test_paper_fourier_m16_many_half_turns_operators():
+    """The paper's M = 16 Fourier basis (Sec. 6; K = 15 real functions from
+    the library's table) over its 130 half-turns: synthesise-first refuses
+    Npi > 32, so the automatic form choice runs project-first in FP32;
+    forward and adjoint against the FP64 oracle given the same tables."""
+    torch.cuda.set_device(DEV)
+    G = rt4d.Geom(N=40, Nz=2, Ns=44, Ntheta=130 * 3, Npi=130, K=15, Nt=2)
+    phi, S = rt4d.basis_fourier(G, 16)
+    plan = rt4d.Plan(G, form=rt4d.RT_FORM_AUTO, prec=rt4d.RT_PREC_BF16MFMA, phi=phi, S=S)
+    assert (plan.form, plan.prec) == (rt4d.RT_FORM_PF, rt4d.RT_PREC_FP32)
+    f = inputs.uniform(G.f_shape, 74)
+    s = inputs.uniform(G.g_shape, 75)
+    ef = rel(plan.forward(T(f)).cpu().numpy(), O.forward(og(G), f, phi=phi, route="folded"))
+    ea = rel(plan.adjoint(T(s)).cpu().numpy(), O.adjoint(og(G), s, phi=phi, route="folded"))
+    print(f"M=16 over 130 half-turns: forward {ef:.2e} adjoint {ea:.2e}")
+    assert ef <= 1e-5 and ea <= 1e-5
+    plan.close()
+
+
+def test_paper_fourier_m16_solve():
+    """M = 16 (K = 15) with 40 half-turns and the TV on 40 frames: 20
+    iterations of the automatically chosen (project-first FP32) loop against
+    the oracle's, iterate within 1e-3."""
+    torch.cuda.set_device(DEV)
+    G = rt4d.Geom(N=32, Nz=2, Ns=36, Ntheta=40 * 4, Npi=40, K=15, Nt=40)
+    phi, S = rt4d.basis_fourier(G, 16)
+    g = inputs.uniform(G.g_shape, 76, 0.0, 1.0)
+    _, r0 = O.solve(og(G), g, lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=5,
+                    phi=phi, S=S, route="folded")
+    kw = dict(lambda1=2.0 ** -9 * r0["L_R"] ** 2, lambda2=4.0, n_iter=20, tau=r0["tau"],
+              sigma=r0["sigma"])
+    plan = rt4d.Plan(G, form=rt4d.RT_FORM_AUTO, prec=rt4d.RT_PREC_BF16MFMA, phi=phi, S=S)
+    assert plan.form == rt4d.RT_FORM_PF
+    f = torch.zeros(G.f_shape, device=DEV)
+    rep = plan.solve(T(g), f, **kw)
+    fo, ro = O.solve(og(G), g, phi=phi, S=S, route="folded", **kw)
+    e = rel(f.cpu().numpy(), fo)
+    m = float(np.abs(f.cpu().numpy() - fo).max() / np.abs(fo).max())
+    print(f"M=16 solve: rel {e:.2e}, scaled max-abs {m:.2e}")
+    assert e <= 1e-3 and m <= 1e-3
+    assert abs(rep["objective"] - ro["objective"]) <= 1e-4 * abs(ro["objective"])
+    plan.close()

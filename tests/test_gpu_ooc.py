@@ -98,16 +98,17 @@ def test_ooc_against_oracle(variant):
     objective within 1e-4."""
     torch.cuda.set_device(DEV)
     g, f0 = case(G7, 101)
-    kw = dict(lambda1=2.0 ** -9 * 48.0 ** 2, lambda2=4.0, n_iter=8, n_pow=20, seed=3)
+    og = O.Geom(**G7.__dict__)
+    # steps from the oracle's own step rule (20 power steps), given to both
+    _, r0 = O.solve(og, g.numpy(), lambda1=0.0, lambda2=4.0, n_iter=0, n_pow=20, seed=3,
+                    route="folded")
+    kw = dict(lambda1=2.0 ** -9 * 48.0 ** 2, lambda2=4.0, n_iter=8, tau=r0["tau"],
+              sigma=r0["sigma"])
     if variant == "accel":
         kw.update(mu=2.0, variant="accel")
     f = f0.clone()
     ro = rt4d.solve_ooc(G7, g, f, 3, **kw)
-    og = O.Geom(**G7.__dict__)
-    # the oracle takes the library's steps (its own power iteration agrees
-    # to 1e-5; parity is on the iteration)
-    fo, rr = O.solve(og, g.numpy(), f0=f0.numpy(), route="folded",
-                     **{**kw, "tau": ro["tau"], "sigma": ro["sigma"]})
+    fo, rr = O.solve(og, g.numpy(), f0=f0.numpy(), route="folded", **kw)
     a, b = f.numpy().astype(np.float64), fo
     e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
     m = float(np.abs(a - b).max() / np.abs(b).max())

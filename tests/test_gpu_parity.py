@@ -3,9 +3,12 @@
 Tolerances: tables bit-exact; operators rel-L2 <= 1e-5 (FP32 arithmetic
 against FP64) and <= 3e-3 with the BF16 contraction; TV operators <= 1e-6;
 reconstructions after a fixed iteration count rel-L2 <= 1e-3, in both forms.
-Every array comparison also bounds the largest element error: max |got - want|
-<= tol * max |want| (the same tolerance, scaled by the largest reference
-value), so that a few wrong elements cannot hide in the norm."""
+Every array comparison also bounds the largest element error, scaled by the
+largest reference value, so that a few wrong elements cannot hide in the norm:
+max |got - want| <= tol * max |want| for FP32 results, and <= BF16_ELEM for
+every result that passes through the BF16 contraction (the operator bar of that
+form: one rounding of f~ to BF16 moves an element by up to 2^-9 of itself,
+about 2e-3, which the norm averages and a single element does not)."""
 import numpy as np
 import pytest
 import torch
@@ -24,15 +27,21 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def close(got, want, tol, what=""):
-    """rel-L2 <= tol and max |got - want| <= tol * max |want|; returns both."""
+BF16_ELEM = 3e-3   # element bar of results that pass through the BF16 contraction
+
+
+def close(got, want, tol, what="", elem=None):
+    """rel-L2 <= tol and max |got - want| <= elem * max |want| (elem defaults
+    to tol); returns both."""
+    elem = tol if elem is None else elem
     a = np.asarray(got, np.float64)
     b = np.asarray(want, np.float64)
     assert a.shape == b.shape, (what, a.shape, b.shape)
     e = rel(a, b)
     m = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) if b.size else 0.0
-    print(f"  {what}: rel-L2 {e:.2e}, scaled max-abs {m:.2e} (tol {tol:.0e})", flush=True)
-    assert e <= tol and m <= tol, (what, e, m, tol)
+    print(f"  {what}: rel-L2 {e:.2e} (tol {tol:.0e}), scaled max-abs {m:.2e} (tol {elem:.0e})",
+          flush=True)
+    assert e <= tol and m <= elem, (what, e, m, tol, elem)
     return e, m
 
 
@@ -352,7 +361,7 @@ def test_precision_form_line_parts():
     f_sf = torch.zeros(G.f_shape, device=DEV)
     r_sf = p.solve(T(g0), f_sf, **kw)
     fo, ro = O.solve(og(G), g0, route="folded", **kw)
-    close(f_sf.cpu().numpy(), fo, 1e-3, "line parts: precision solve iterate")
+    close(f_sf.cpu().numpy(), fo, 1e-3, "line parts: precision solve iterate", BF16_ELEM)
     print(f"line parts: residual {r_sf['residual']:.9e} vs {ro['residual']:.9e}", flush=True)
     assert abs(r_sf["residual"] - ro["residual"]) <= 3e-3 * ro["residual"]
 
@@ -370,7 +379,7 @@ def test_precision_form_solve_c1():
     rep = p.solve(T(g), f, **kw)
     fo, ro = O.solve(og(G), g, route="folded", **kw)
     print(f"precision-form C1 solve: objective {rep['objective']:.6e} vs {ro['objective']:.6e}")
-    close(f.cpu().numpy(), fo, 1e-3, "precision-form C1 solve iterate")
+    close(f.cpu().numpy(), fo, 1e-3, "precision-form C1 solve iterate", BF16_ELEM)
     assert abs(rep["objective"] - ro["objective"]) <= 1e-3 * abs(ro["objective"])
 
 
