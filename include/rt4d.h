@@ -280,6 +280,18 @@ void rt_job_destroy(rt_job *job);
  * with a fixed tree; blocks on `stream`.  y may equal x. */
 int rt_dot(const float *x, const float *y, size_t n, double *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rt_dot with
+ * its partial sums in a static device array of the library (2049 doubles per
+ * GPU, held until the process ends) instead of a per-call allocation.  Same
+ * arguments, result and summation order as rt_dot (bitwise equal).  The
+ * array holds the partials of the widest reduction launch (2048 workgroups,
+ * whatever n), so no n is too large; a launch that needed more would fail
+ * with RT_E_SHAPE.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  Blocks on `stream` for the result. */
+int rt_dot_noalloc(const float *x, const float *y, size_t n, double *out, void *stream);
+
 /* ---- per-kernel timing --------------------------------------------------
  * When enabled, every kernel launch records a HIP event pair on its stream.
  * rt_timing_read sums the elapsed times of all recorded launches of the

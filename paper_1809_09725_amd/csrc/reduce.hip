@@ -5,6 +5,9 @@
 // __shfl_xor, then the four wave sums in order) and write one partial; one
 // workgroup then sums the partials in a fixed order.  The grid size depends
 // only on n, so the result is bitwise reproducible for a given shape.
+#include <mutex>
+#include <unordered_map>
+
 #include "common.h"
 #include "internal.h"
 
@@ -144,6 +147,67 @@ int launch_seeded_uniform(float *x, size_t n, uint64_t seed, hipStream_t s)
 }
 
 }  // namespace rt
+
+// ---- the allocation-free variant of rt_dot -------------------------------
+// Its partials live in a file-scope device array instead of a per-call
+// allocation.  In host code `scratch` names a host-side stand-in, not device
+// memory: the device address comes from hipGetSymbolAddress, once per device
+// with that device current, and only that address is passed to kernels.
+namespace rt {
+namespace {
+
+constexpr int DOT_MAX_PARTIALS = 2048;   // grid_for(n, 2048): the widest reduction launch
+__device__ __align__(256) double scratch[DOT_MAX_PARTIALS + 1];   // partials, then the sum
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, double *> g_scratch_ptr;   // device -> address of its copy
+
+int scratch_ptr(double **out)
+{
+    int dev = 0;
+    RT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "rt_dot_noalloc: hipGetSymbolAddress(scratch)");
+        it = g_scratch_ptr.emplace(dev, (double *)p).first;
+    }
+    *out = it->second;
+    return RT_OK;
+}
+
+}  // namespace
+}  // namespace rt
+
+extern "C" int rt_dot_noalloc(const float *x, const float *y, size_t n, double *out, void *stream)
+{
+    using namespace rt;
+    if (!out || (n && (!x || !y))) return fail(RT_E_ARG, "rt_dot_noalloc: NULL argument");
+    if (n == 0) {
+        *out = 0.0;
+        return RT_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = reduce_blocks(0, n);
+    if (nb > DOT_MAX_PARTIALS)
+        return fail(RT_E_SHAPE, "rt_dot_noalloc: %d partials exceed the static scratch of %d", nb,
+                    DOT_MAX_PARTIALS);
+    double *part = nullptr;
+    int rc = scratch_ptr(&part);
+    if (rc) return rc;
+    double *res = part + nb;
+    // every partial is written before k_finish reads it: nothing to clear
+    rc = launch_dot_partials(x, y, n, part, nb, s);
+    if (!rc) rc = launch_finish(part, nb, 1, res, s);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "rt_dot_noalloc readback");
+    }
+    return rc;
+}
 
 extern "C" int rt_dot(const float *x, const float *y, size_t n, double *out, void *stream)
 {

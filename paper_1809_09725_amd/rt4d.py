@@ -31,7 +31,7 @@ EXPORTS = ("rt_plan_create", "rt_plan_destroy", "rt_plan_bytes", "rt_tables", "r
            "rt_job_create", "rt_job_step", "rt_job_done", "rt_job_iters", "rt_job_report",
            "rt_job_checkpoint_bytes", "rt_job_checkpoint", "rt_job_restore", "rt_job_destroy",
            "rt_dot", "rt_timing_enable", "rt_timing_reset", "rt_timing_read", "rt_last_error",
-           "rt_fbp_filter", "rt_fbp", "rt_solve_ooc", "rt_calib_fma", "rt_form_pick", "rt_plan_form", "rt_basis_fourier")
+           "rt_fbp_filter", "rt_fbp", "rt_solve_ooc", "rt_calib_fma", "rt_form_pick", "rt_plan_form", "rt_basis_fourier", "rt_dot_noalloc")
 
 
 class RtError(RuntimeError):
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "rt_job_restore": (c_int, [vp, vp, vp]),
         "rt_job_destroy": (None, [vp]),
         "rt_dot": (c_int, [vp, vp, sz, P(ctypes.c_double), vp]),
+        "rt_dot_noalloc": (c_int, [vp, vp, sz, P(ctypes.c_double), vp]),
         "rt_fbp_filter": (c_int, [vp, vp, vp, vp]),
         "rt_fbp": (c_int, [vp, vp, vp, vp]),
         "rt_solve_ooc": (c_int, [P(rt_geom), vp, vp, P(rt_solve_params), vp, vp, i32,
