@@ -48,6 +48,13 @@ struct Tables {
 // Work layout of the ray-driven projector: classes of one walk direction
 // (rows when |cos| >= |sin|, columns otherwise) are grouped A at a time; one
 // workgroup owns (group, slice, channel chunk, bin tile).
+// Staged lines of the plain projector: KC channels of a position in a row of
+// line_stride(KC) floats (an odd number of 16-byte groups, so that 16
+// consecutive positions fall in distinct LDS bank groups), LINE_GUARD zero
+// positions at each end of a line.
+constexpr int LINE_GUARD = 2;
+__host__ __device__ constexpr int line_stride(int kc) { return (kc / 4) % 2 ? kc : kc + 4; }
+
 struct FwdCfg {
     int A = 1;            // classes per group
     int ngroups = 0;

@@ -164,9 +164,9 @@ static int configure(Plan &p)
         const int pfmax = g.K % 4 == 0 && !wide ? 8 : 4;   // float4 of line prefetch per thread
         const int kcmax = g.K % 4 == 0 && g.N <= 512 ? 16 : 8;
         if (F.KC || (kc > K4 && kc != 4) || g.N * kc > 4 * pfmax * 512 || kc > kcmax) continue;
-        const int stride = (kc / 4) % 2 ? kc : kc + 4;
+        const int stride = line_stride(kc);
         for (int nbuf : {2, 1})
-            if (!F.KC && nbuf * (size_t)(g.N + 2) * stride * sizeof(float) <= 160 * 1024) {
+            if (!F.KC && nbuf * (size_t)(g.N + 2 * LINE_GUARD) * stride * sizeof(float) <= 160 * 1024) {
                 F.KC = kc;
                 F.stride = stride;
                 F.nbuf = nbuf;
@@ -178,7 +178,7 @@ static int configure(Plan &p)
     F.tl = g.N > 512;
     F.nkc = (g.K + F.KC - 1) / F.KC;
     F.vec = (g.K % 4 == 0) ? 4 : 1;
-    F.lds = (size_t)F.nbuf * (g.N + 2) * F.stride * sizeof(float);
+    F.lds = (size_t)F.nbuf * (g.N + 2 * LINE_GUARD) * F.stride * sizeof(float);
     // 16-channel chunks over more than 1024 rays: 1024 threads of 2 rays each.
     // The group (and so the slice re-read traffic) is the same as with 512
     // threads of 4 rays, at half the registers per thread, so twice the

@@ -26,19 +26,38 @@ namespace rt {
 namespace {
 
 constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
+constexpr int G0 = LINE_GUARD;   // zero guard positions at each end of a staged line
 
 // Staging of one line (row or column of a slice, KC channels, positions
-// 0..N-1 into LDS slots 1..N) through registers: the loads of line l+1 are
-// issued before the taps of line l are summed, and written to the other LDS
-// buffer afterwards (or, with one buffer, over line l once its taps are done).  PF float4 per thread cover a whole line
-// (N * KC <= 4 * PF * FT).  VEC = 4: float4 loads (K % 4 == 0); VEC = 1:
-// scalar loads of the same PF*4 values.
+// 0..N-1 into LDS slots G0..N+G0-1; slots 0..G0-1 and N+G0..N+2G0-1 stay zero)
+// through registers: the loads of line l+1 are issued before the taps of line
+// l are summed, and written to the other LDS buffer afterwards (or, with one
+// buffer, over line l once its taps are done).  PF float4 per thread cover a
+// whole line (N * KC <= 4 * PF * NTH).  VEC = 4: float4 loads (K % 4 == 0);
+// VEC = 1: scalar loads of the same PF*4 values.  EXACT: the PF float4 of the
+// NTH threads are exactly the line's N * KC values and every channel of the
+// chunk exists (N * KC == 4 * PF * NTH, K % KC == 0), so the loads need no
+// masks; element j of a thread is then at offset off + j * inc of the line
+// (32-bit: at most N * N * K < 2^31 floats) and at LDS float dst + j * dinc.
 template <int KC, int PF, int VEC, int NTH>
 struct LinePrefetch {
     float4 r[PF];
-    __device__ inline void load(const float *__restrict__ src, size_t pstep, int N, int k0, int K)
+    // EXACT: the offsets of element 0 of this thread (line float, LDS float)
+    // and their steps between elements (uniform)
+    struct Exact {
+        int off, inc, dst, dinc;
+    };
+    static __device__ inline Exact exact(size_t pstep)
     {
-        if (VEC == 4) {
+        constexpr int NQ = KC / 4;
+        const int pos = threadIdx.x / NQ, kq = threadIdx.x % NQ;
+        return {pos * (int)pstep + 4 * kq, (NTH / NQ) * (int)pstep,
+                (pos + G0) * line_stride(KC) + 4 * kq, (NTH / NQ) * line_stride(KC)};
+    }
+    __device__ inline void load(const float *__restrict__ src, size_t pstep, int N, int k0, int K,
+                                const Exact &)
+    {
+        if constexpr (VEC == 4) {
             constexpr int NQ = KC / 4;
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
@@ -61,15 +80,16 @@ struct LinePrefetch {
             }
         }
     }
-    __device__ inline void store(float *__restrict__ buf, int N, int stride) const
+    __device__ inline void store(float *__restrict__ buf, int N, const Exact &) const
     {
-        if (VEC == 4) {
+        constexpr int stride = line_stride(KC);
+        if constexpr (VEC == 4) {
             constexpr int NQ = KC / 4;
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
                 const int e = threadIdx.x + NTH * j;
                 const int pos = e / NQ, kq = e % NQ;
-                if (pos < N) *(float4 *)(buf + (pos + 1) * stride + 4 * kq) = r[j];
+                if (pos < N) *(float4 *)(buf + (pos + G0) * stride + 4 * kq) = r[j];
             }
         } else {
 #pragma unroll
@@ -79,7 +99,7 @@ struct LinePrefetch {
                 for (int i = 0; i < 4; ++i) {
                     const int e = threadIdx.x + NTH * (4 * j + i);
                     const int pos = e / KC, kk = e % KC;
-                    if (pos < N) buf[(pos + 1) * stride + kk] = v[i];
+                    if (pos < N) buf[(pos + G0) * stride + kk] = v[i];
                 }
             }
         }
@@ -112,15 +132,15 @@ __device__ inline int fwd_ray(int pr, int a, const unsigned char *__restrict__ l
     return lperm && a >= 0 ? (pr & ~63) | (int)lperm[a * 64 + (pr & 63)] : pr;
 }
 
-template <int KC, int PPT, int PF, int VEC, bool TL, int NTH>
+template <int KC, int PPT, int PF, int VEC, bool TL, int NTH, bool EXACT>
 __global__ __launch_bounds__(NTH) void k_project(
     const float *__restrict__ f, float *__restrict__ P, const int *__restrict__ gcls,
     const int *__restrict__ gwalk, const unsigned char *__restrict__ lperm,
     const double *__restrict__ ccos, const double *__restrict__ csin, int N, int Nz, int Ns,
-    int K, int A, int ngroups, int BT, int nbt, int nkc, int stride, int nbuf, unsigned nblocks,
-    FwdEpi E)
+    int K, int A, int ngroups, int BT, int nbt, int nkc, int nbuf, unsigned nblocks, FwdEpi E)
 {
-    extern __shared__ float lines[];   // nbuf buffers x [N + 2 slots][stride], slots = positions -1 .. N
+    constexpr int stride = line_stride(KC);
+    extern __shared__ float lines[];   // nbuf buffers x [N + 2 G0 slots][stride], slot = position + G0
     __shared__ double sh[NTH / 64];
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int bt = lid % nbt;
@@ -133,30 +153,39 @@ __global__ __launch_bounds__(NTH) void k_project(
     const int walk = gwalk[grp];
     const int k0 = kc * KC;
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
-    const int bufsz = (N + 2) * stride;
+    const int bufsz = (N + 2 * G0) * stride;
 
-    double base[PPT], slope[PPT];
-    float invc[PPT];
+    // Ray positions along the lines in 32.32 fixed point: u(l) = u(0) + l s,
+    // stepped by an exact integer add per line, so u(l) carries the rounding
+    // of u(0) and of l s alone (below 2^-32 (1 + l) positions).  Its integer
+    // part is the left tap, its fraction the interpolation weight.  A ray
+    // outside the tile has 1/c = 0; a position before the line or past it is
+    // clamped into the zero guard slots.
+    long long U[PPT], S[PPT];
+    float invc[PPT], sfr[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int slot = (tid + NTH * j) / BT;
         const int a = slot < A ? gcls[grp * A + slot] : -1;
         const int b = bt * BT + fwd_ray(tid + NTH * j, a, lperm) % BT;
-        base[j] = -1.0e9;   // far outside: both taps get weight 0
-        slope[j] = 0.0;
+        double base = -1.0e6, slope = 0.0;
         invc[j] = 0.f;
         if (a >= 0 && b < Ns) {
             const double cs = ccos[a], sn = csin[a], sb = (double)b - hS;
             if (walk == 0) {   // |cos| >= |sin|: the ray crosses every row once
-                base[j] = sb / cs + hN;
-                slope[j] = -sn / cs;
+                base = sb / cs + hN;
+                slope = -sn / cs;
                 invc[j] = (float)(1.0 / fabs(cs));
             } else {           // |sin| > |cos|: every column once
-                base[j] = sb / sn + hN;
-                slope[j] = -cs / sn;
+                base = sb / sn + hN;
+                slope = -cs / sn;
                 invc[j] = (float)(1.0 / fabs(sn));
             }
         }
+        const double u0 = fmin(fmax(fma(-hN, slope, base), -1.0e6), 1.0e6);   // line 0
+        U[j] = (long long)llrint(u0 * 4294967296.0);
+        S[j] = (long long)llrint(slope * 4294967296.0);
+        sfr[j] = invc[j] * 2.3283064365386963e-10f;   // fraction bits -> weight: 2^-32 / c
     }
 
     // TL (two-level sums, planned for N > 512): the taps of LB consecutive
@@ -174,35 +203,59 @@ __global__ __launch_bounds__(NTH) void k_project(
 #pragma unroll
         for (int k = 0; k < KC; ++k) blk[j][k] = 0.f;
 
-    for (int e = tid; e < 2 * nbuf * stride; e += NTH) {   // zero slots -1 and N of each buffer
-        const int b = e / (2 * stride), w = e % (2 * stride);
-        lines[b * bufsz + (w < stride ? 0 : (N + 1) * stride) + w % stride] = 0.f;
+    for (int e = tid; e < nbuf * 2 * G0 * stride; e += NTH) {   // zero the guard slots
+        const int b = e / (2 * G0 * stride), w = e % (2 * G0 * stride);
+        const int row = w / stride;
+        lines[b * bufsz + (row < G0 ? row : N + row) * stride + w % stride] = 0.f;
     }
 
-    const size_t zoff = (size_t)z * N * N * K + k0;
     const size_t lstep = walk == 0 ? (size_t)N * K : (size_t)K;   // next line
     const size_t pstep = walk == 0 ? (size_t)K : (size_t)N * K;   // next position
+    const float *src = f + (size_t)z * N * N * K + k0;
 
-    LinePrefetch<KC, PF, VEC, NTH> pf;
-    pf.load(f + zoff, pstep, N, k0, K);
-    pf.store(lines, N, stride);
+    // staging registers: PF float4 per thread, or with EXACT two named float4
+    // at the offsets of Stage::exact (an indexed array there is placed in
+    // scratch memory by the compiler)
+    using Stage = LinePrefetch<KC, PF, VEC, NTH>;
+    Stage pf;
+    const typename Stage::Exact ex = EXACT ? Stage::exact(pstep) : typename Stage::Exact{0, 0, 0, 0};
+    float4 xa, xb;
+    auto stage_load = [&]() {
+        if constexpr (EXACT) {
+            static_assert(PF == 2, "the unmasked staging is planned with 2 float4 per thread");
+            xa = *(const float4 *)(src + ex.off);
+            xb = *(const float4 *)(src + ex.off + ex.inc);
+        } else {
+            pf.load(src, pstep, N, k0, K, ex);
+        }
+    };
+    auto stage_store = [&](float *buf) {
+        if constexpr (EXACT) {
+            *(float4 *)(buf + ex.dst) = xa;
+            *(float4 *)(buf + ex.dst + ex.dinc) = xb;
+        } else {
+            pf.store(buf, N, ex);
+        }
+    };
+    stage_load();
+    stage_store(lines);
     __syncthreads();
 
     for (int l = 0; l < N; ++l) {
         const bool more = l + 1 < N;
-        if (more) pf.load(f + zoff + (size_t)(l + 1) * lstep, pstep, N, k0, K);
+        if (more) {
+            src += lstep;
+            stage_load();
+        }
         const float *line = lines + (nbuf == 2 ? (l & 1) * bufsz : 0);
-        const double lc = (double)l - hN;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const double u = fma(lc, slope[j], base[j]);   // position along the line
-            const double fl = floor(u);
-            const int q0 = (int)fl;
-            const float fr = (float)(u - fl);
-            const bool in = (unsigned)(q0 + 1) <= (unsigned)N;   // -1 <= q0 <= N-1
-            const float w1 = in ? fr * invc[j] : 0.f;
-            const float w0 = in ? (1.f - fr) * invc[j] : 0.f;
-            const float *t0 = line + (in ? q0 + 1 : 0) * stride;
+            const int q0 = (int)(U[j] >> 32);
+            const float fr = (float)(unsigned)U[j];
+            U[j] += S[j];
+            const float w1 = fr * sfr[j];
+            const float w0 = invc[j] - w1;
+            const float *t0 = line + __mul24(min(max(q0, -G0), N) + G0, stride);
             // the taps of this ray into s (the ray's sums or its block sums);
             // its FMAs finish before the next ray's tap loads are issued:
             // hoisting the loads of all rays needs 32 VGPRs per ray and spills
@@ -236,7 +289,7 @@ __global__ __launch_bounds__(NTH) void k_project(
         // line l+1 goes to the other buffer while l is read; with one buffer,
         // after every thread's taps of line l
         if (nbuf == 1) __syncthreads();
-        if (more) pf.store(lines + (nbuf == 2 ? ((l + 1) & 1) * bufsz : 0), N, stride);
+        if (more) stage_store(lines + (nbuf == 2 ? ((l + 1) & 1) * bufsz : 0));
         __syncthreads();
     }
 
@@ -383,20 +436,20 @@ __global__ __launch_bounds__(NT) void k_fold(const float *__restrict__ g,
     }
 }
 
-template <int KC, int PPT, int PF, int VEC, bool TL, int NTH = FT>
+template <int KC, int PPT, int PF, int VEC, bool TL, int NTH = FT, bool EXACT = false>
 static int launch_project_t(const Plan &p, const float *f, const FwdEpi &E, hipStream_t s,
                             unsigned nb)
 {
     const rt_geom &G = p.g;
     const FwdCfg &F = p.fwd;
-    auto kern = k_project<KC, PPT, PF, VEC, TL, NTH>;
+    auto kern = k_project<KC, PPT, PF, VEC, TL, NTH, EXACT>;
     if (F.lds > 64 * 1024)   // beyond the default dynamic LDS limit: ask for what this plan needs
         RT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)F.lds));
     KTimer kt("k_project", s);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(NTH), F.lds, s, f, p.d_scr, p.d_gcls, p.d_gwalk,
                        F.BT % 64 == 0 ? p.d_lperm : nullptr, p.d_ccos, p.d_csin, G.N, G.Nz, G.Ns, G.K, F.A, F.ngroups, F.BT, F.nbt,
-                       F.nkc, F.stride, F.nbuf, nb, E);
+                       F.nkc, F.nbuf, nb, E);
     kt.stop();
     return RT_OK;
 }
@@ -484,7 +537,12 @@ int launch_forward_pf(const Plan &p, const float *f, float *g, int mode, const f
         // lines of at most 512 positions (2 float4 of prefetch per thread)
         if (F.vec != 4 || F.KC != 16 || ppt != 2 || F.tl || G.N * 16 > 4 * 2 * 2 * FT)
             return fail(RT_E_SHAPE, "no 1024-thread projection kernel for this plan");
-        rc = launch_project_t<16, 2, 2, 4, false, 2 * FT>(p, f, E, s, nb);
+        // the 2 float4 of the 1024 threads are exactly a line of 512 positions
+        // when N = 512 and every chunk holds 16 channels: unmasked staging
+        if (G.N == 512 && G.K % 16 == 0)
+            rc = launch_project_t<16, 2, 2, 4, false, 2 * FT, true>(p, f, E, s, nb);
+        else
+            rc = launch_project_t<16, 2, 2, 4, false, 2 * FT>(p, f, E, s, nb);
     } else if (F.vec == 4) {
         switch (F.KC) {
         case 4: rc = launch_project_k<4, 4>(p, f, E, s, nb, ppt); break;
