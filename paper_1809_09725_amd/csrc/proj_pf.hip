@@ -28,6 +28,15 @@ namespace {
 constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
 constexpr int G0 = LINE_GUARD;   // zero guard positions at each end of a staged line
 
+// clamp to [lo, hi] in one v_med3_i32 (the compiler forms it only for
+// constant bounds)
+__device__ inline int clamp_i32(int x, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 // Staging of one line (row or column of a slice, KC channels, positions
 // 0..N-1 into LDS slots G0..N+G0-1; slots 0..G0-1 and N+G0..N+2G0-1 stay zero)
 // through registers: the loads of line l+1 are issued before the taps of line
@@ -154,6 +163,7 @@ __global__ __launch_bounds__(NTH) void k_project(
     const int k0 = kc * KC;
     const double hN = 0.5 * (double)(N - 1), hS = 0.5 * (double)(Ns - 1);
     const int bufsz = (N + 2 * G0) * stride;
+    if constexpr (EXACT) nbuf = 2;   // planned so (a 512-position line of 16 channels)
 
     // Ray positions along the lines in 32.32 fixed point: u(l) = u(0) + l s,
     // stepped by an exact integer add per line, so u(l) carries the rounding
@@ -255,7 +265,7 @@ __global__ __launch_bounds__(NTH) void k_project(
             U[j] += S[j];
             const float w1 = fr * sfr[j];
             const float w0 = invc[j] - w1;
-            const float *t0 = line + __mul24(min(max(q0, -G0), N) + G0, stride);
+            const float *t0 = line + __umul24((unsigned)(clamp_i32(q0, -G0, N) + G0), (unsigned)stride);
             // the taps of this ray into s (the ray's sums or its block sums);
             // its FMAs finish before the next ray's tap loads are issued:
             // hoisting the loads of all rays needs 32 VGPRs per ray and spills
@@ -308,9 +318,15 @@ __global__ __launch_bounds__(NTH) void k_project(
                 if (k0 + k < K) dst[k] = acc[j][k];
             continue;
         }
-        for (int r = 0; r < E.Npi; ++r) {   // every half-turn of class a (K <= KC here)
+        // every half-turn of class a (K <= KC here); out, gdata and phi do not
+        // overlap, so the loads of all half-turns may be issued ahead of the
+        // stores
+        const float *__restrict__ phi = E.phi;
+        const float *__restrict__ gd = E.gdata;
+        float *__restrict__ out = E.out;
+        for (int r = 0; r < E.Npi; ++r) {
             const int i = r * E.n0 + a;
-            const float *ph = E.phi + (size_t)i * K;
+            const float *ph = phi + (size_t)i * K;
             float v = 0.f;
 #pragma unroll
             for (int k = 0; k < KC; ++k)
@@ -318,11 +334,11 @@ __global__ __launch_bounds__(NTH) void k_project(
             const int bo = (r & 1) ? Ns - 1 - b : b;
             const size_t o = ((size_t)i * Nz + z) * Ns + bo;
             if (E.mode == EPI_G) {
-                E.out[o] = v;
+                out[o] = v;
             } else {
-                const float d = v - E.gdata[o];
+                const float d = v - gd[o];
                 d2 += (double)d * (double)d;
-                E.out[o] = (E.out[o] + E.sigma * d) * inv1s;
+                out[o] = (out[o] + E.sigma * d) * inv1s;
             }
         }
     }
