@@ -443,7 +443,8 @@ def roofline_of(per: dict, G, sf: bool, workload: str) -> tuple[dict, dict]:
         b, w = algorithmic(k, G, sf)
         d = ms / n * 1e-3
         kern[k] = {"ms": round(d * 1e3, 4), "bound": b,
-                   "frac": round((w / d) / (PEAK_HBM if b == "hbm" else PEAK_FP32_VALU), 4)}
+                   "frac": round((w / d) / (PEAK_HBM if b == "hbm" else PEAK_FP32_VALU), 4),
+                   "traffic": traffic_from_profiles(k, workload)}
     return roof, kern
 
 
