@@ -269,15 +269,26 @@ __global__ __launch_bounds__(NTH) void k_project(
             // the taps of this ray into s (the ray's sums or its block sums);
             // its FMAs finish before the next ray's tap loads are issued:
             // hoisting the loads of all rays needs 32 VGPRs per ray and spills
+            // The left tap's channels are read (and summed) before the right
+            // tap's: a wave's consecutive LDS reads then stay on one staged
+            // row, which measured 7% faster than alternating the two rows.
+            // Each channel still adds w0 x0, then w1 x1.
             auto taps = [&](float (&sr)[KC]) {
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {
                     const float4 x0 = *(const float4 *)(t0 + k);
+                    sr[k + 0] = fmaf(w0, x0.x, sr[k + 0]);
+                    sr[k + 1] = fmaf(w0, x0.y, sr[k + 1]);
+                    sr[k + 2] = fmaf(w0, x0.z, sr[k + 2]);
+                    sr[k + 3] = fmaf(w0, x0.w, sr[k + 3]);
+                }
+#pragma unroll
+                for (int k = 0; k < KC; k += 4) {
                     const float4 x1 = *(const float4 *)(t0 + stride + k);
-                    sr[k + 0] = fmaf(w1, x1.x, fmaf(w0, x0.x, sr[k + 0]));
-                    sr[k + 1] = fmaf(w1, x1.y, fmaf(w0, x0.y, sr[k + 1]));
-                    sr[k + 2] = fmaf(w1, x1.z, fmaf(w0, x0.z, sr[k + 2]));
-                    sr[k + 3] = fmaf(w1, x1.w, fmaf(w0, x0.w, sr[k + 3]));
+                    sr[k + 0] = fmaf(w1, x1.x, sr[k + 0]);
+                    sr[k + 1] = fmaf(w1, x1.y, sr[k + 1]);
+                    sr[k + 2] = fmaf(w1, x1.z, sr[k + 2]);
+                    sr[k + 3] = fmaf(w1, x1.w, sr[k + 3]);
                 }
 #pragma unroll
                 for (int k = 0; k < KC; ++k) asm volatile("" : "+v"(sr[k])::"memory");
@@ -324,21 +335,44 @@ __global__ __launch_bounds__(NTH) void k_project(
         const float *__restrict__ phi = E.phi;
         const float *__restrict__ gd = E.gdata;
         float *__restrict__ out = E.out;
-        for (int r = 0; r < E.Npi; ++r) {
-            const int i = r * E.n0 + a;
-            const float *ph = phi + (size_t)i * K;
-            float v = 0.f;
+        // Channels k >= K of the chunk were staged as zeros, so their sums
+        // are exactly 0 and a clamped (in-bounds) Phi index leaves v as it
+        // is.  The half-turns go in groups of HG whose loads (Phi rows, and
+        // for the prox g and h1) are all issued before any of them is used:
+        // with one workgroup per CU the epilogue's memory round trips are not
+        // hidden by other work, and a branch per channel or a round trip per
+        // half-turn cost up to 1 ms per launch.  Lanes past the last
+        // half-turn load that half-turn again and store nothing.
+        constexpr int HG = KC >= 16 ? 2 : 32 / KC;   // HG * KC <= 32 Phi values in registers
+        for (int r0 = 0; r0 < E.Npi; r0 += HG) {
+            float ph[HG][KC], gv[HG], hv[HG];
+            size_t o[HG];
 #pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < K) v = fmaf(ph[k], acc[j][k], v);
-            const int bo = (r & 1) ? Ns - 1 - b : b;
-            const size_t o = ((size_t)i * Nz + z) * Ns + bo;
-            if (E.mode == EPI_G) {
-                out[o] = v;
-            } else {
-                const float d = v - gd[o];
-                d2 += (double)d * (double)d;
-                out[o] = (out[o] + E.sigma * d) * inv1s;
+            for (int u = 0; u < HG; ++u) {
+                const int r = min(r0 + u, E.Npi - 1);
+                const int i = r * E.n0 + a;
+                const float *row = phi + (size_t)i * K;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) ph[u][k] = row[k < K ? k : K - 1];
+                o[u] = ((size_t)i * Nz + z) * Ns + ((r & 1) ? Ns - 1 - b : b);
+                if (E.mode != EPI_G) {
+                    gv[u] = gd[o[u]];
+                    hv[u] = out[o[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < HG; ++u) {
+                if (r0 + u >= E.Npi) break;
+                float v = 0.f;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) v = fmaf(ph[u][k], acc[j][k], v);
+                if (E.mode == EPI_G) {
+                    out[o[u]] = v;
+                } else {
+                    const float d = v - gv[u];
+                    d2 += (double)d * (double)d;
+                    out[o[u]] = (hv[u] + E.sigma * d) * inv1s;
+                }
             }
         }
     }

@@ -292,6 +292,10 @@ __global__ __launch_bounds__(ST) void k_project_sf(
     // ---- epilogue: every half-turn r of class a lands on bin b (even r) or Ns-1-b (odd r)
     double d2 = 0.0;
     const float inv1s = 1.f / (1.f + E.sigma);
+    // out and gdata do not overlap: the loads of all half-turns may be issued
+    // ahead of the stores
+    const float *__restrict__ gd = E.gdata;
+    float *__restrict__ out = E.out;
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
         const int j = rho / UB;
@@ -306,11 +310,11 @@ __global__ __launch_bounds__(ST) void k_project_sf(
             const size_t o = ((size_t)i * Nz + z) * Ns + bo;
             const float v = acc[rho][r];
             if (!E.prox) {
-                E.out[o + lp * E.pstride] = v;
+                out[o + lp * E.pstride] = v;
             } else {
-                const float d = v - E.gdata[o];
+                const float d = v - gd[o];
                 d2 += (double)d * (double)d;
-                E.out[o] = (E.out[o] + E.sigma * d) * inv1s;
+                out[o] = (out[o] + E.sigma * d) * inv1s;
             }
         }
     }
