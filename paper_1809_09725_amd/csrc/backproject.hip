@@ -7,7 +7,10 @@
 // A 32x32 pixel tile takes the classes in rounds of CA; each round stages in
 // LDS the window of detector bins the tile's pixels reach for each class
 // (all KC channels of a bin in one row), then every pixel takes the two bins
-// around its s_p for each class.  Positions in FP64, weights and sums in FP32.
+// around its s_p for each class.  A pixel's position relative to its class's
+// window is formed in FP64 once per class and stepped over the thread's rows
+// in 32.32 fixed point (the integer part is the window row, the fraction
+// gives the weights); weights and sums in FP32.
 #include "common.h"
 #include "internal.h"
 
@@ -32,10 +35,12 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
 {
     constexpr int stride = KC + 4;   // an odd number of 16-byte groups per bin
     extern __shared__ float win[];   // [CA][WMAX][stride]
-    __shared__ int s_wlo[BP_MAXCA];
     __shared__ int s_wb[BP_MAXCA], s_we[BP_MAXCA];   // window rows [wb, we) hold bins 0..Ns-1
     __shared__ long long s_goff[BP_MAXCA];           // element offset of window row 0's bin in gt
-    __shared__ float s_inv[BP_MAXCA], s_inv2[BP_MAXCA];   // 1/c and 1/c^2, c = max(|cos|, |sin|)
+    __shared__ float s_inv[BP_MAXCA];                     // 1/c, c = max(|cos|, |sin|)
+    __shared__ float s_ic01[BP_MAXCA], s_s2[BP_MAXCA];    // 1/c - 1/c^2 and 2^-32 / c^2
+    __shared__ double s_base[BP_MAXCA];                   // hS - (bin of window row 0)
+    __shared__ long long s_D[BP_MAXCA];                   // 8 sin in 32.32 fixed point
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
     const int tq = lid % ntq;
     lid /= ntq;
@@ -77,13 +82,15 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             // over its rows, may round an ulp outside [umin, umax]
             const int lo = (int)floor(umin) - 1;
             const int wn = (int)floor(umax) + 3 - lo;
-            s_wlo[tid] = lo;
             s_wb[tid] = max(0, -lo);
             s_we[tid] = min(wn, Ns - lo);
             s_goff[tid] = (((long long)(a0 + tid) * Nz + z) * Ns + lo) * K + k0;
             const double ic = 1.0 / fmax(fabs(cs), fabs(sn));
             s_inv[tid] = (float)ic;
-            s_inv2[tid] = (float)(ic * ic);
+            s_ic01[tid] = (float)ic - (float)(ic * ic);
+            s_s2[tid] = (float)(ic * ic) * 2.3283064365386963e-10f;
+            s_base[tid] = hS - (double)lo;
+            s_D[tid] = (long long)llrint(sn * 34359738368.0);
         }
         __syncthreads();
         if (VEC == 4) {
@@ -122,20 +129,31 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
         __syncthreads();
         for (int c = 0; c < nca; ++c) {
             const double cs = ccos[a0 + c], sn = csin[a0 + c];
-            const float invc = s_inv[c], invc2 = s_inv2[c], ic01 = invc - invc2;
-            const int cw = c * WMAX - s_wlo[c];   // window row of bin b: cw + b
-            // s_p in bin units for the thread's first row; rows 8 apart add 8 sin
-            const double u0 = fma(x, cs, fma(y0, sn, hS)), du = 8.0 * sn;
+            const float invc = s_inv[c], ic01 = s_ic01[c], s2 = s_s2[c];
+            // s_p minus the bin of the window's row 0, for the thread's first
+            // row: at least 1 up to FP64 rounding (the window keeps a spare bin
+            // below the tile's lowest position), so truncation is floor
+            const double rel = fma(x, cs, fma(y0, sn, s_base[c]));
+            const unsigned hi = (unsigned)rel;
+            const unsigned lo = (unsigned)((rel - (double)hi) * 4294967296.0);
+            // 32.32 fixed point whose integer part is the LDS row (class c's
+            // rows start at c WMAX); rows 8 apart add 8 sin, rounded to 2^-32,
+            // which moves a position by at most 2^-31 over the thread's rows
+            unsigned long long U = ((unsigned long long)(hi + (unsigned)(c * WMAX)) << 32) | lo;
+            const unsigned long long D = (unsigned long long)s_D[c];
 #pragma unroll
             for (int j = 0; j < BP_VPT; ++j) {
-                const double u = u0 + (double)j * du;
-                const double fl = floor(u);
-                const float fr = (float)(u - fl);
+                if (j) {
+                    U += D;
+                    asm volatile("" : "+v"(U));   // one 64-bit add per row, not j*D
+                }
+                const unsigned row = (unsigned)(U >> 32);
+                const float fq = (float)(unsigned)U;   // the fraction in units of 2^-32
                 // triangle weights of the bins floor(u) and floor(u)+1,
                 // max(0, 1 - |s_b - s_p| / c) / c = max(0, 1/c - |s_b - s_p| / c^2)
-                const float w0 = fmaxf(0.f, fmaf(-fr, invc2, invc));
-                const float w1 = fmaxf(0.f, fmaf(fr, invc2, ic01));
-                const float *t0 = win + __mul24(cw + (int)fl, stride);
+                const float w0 = fmaxf(0.f, fmaf(-fq, s2, invc));
+                const float w1 = fmaxf(0.f, fmaf(fq, s2, ic01));
+                const float *t0 = win + __umul24(row, stride);
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {
                     const float4 x0 = *(const float4 *)(t0 + k);

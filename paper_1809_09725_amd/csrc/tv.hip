@@ -26,6 +26,53 @@ constexpr int ZC = 4;   // consecutive slices per work item of the gradient and 
 // consecutive voxels read with ds_read_b32 hit 32 different banks.
 __host__ __device__ constexpr int kstride(int KT) { return KT + 1; }
 
+// The arithmetic of one voxel and frame (explicit fmaf throughout: no
+// contraction choice is left to the compiler, so every kernel that takes a
+// step rounds it alike).
+//
+// Dual TV step: a = h + sigma g, h <- a / max(1, |a|_2 / lambda1), as
+// a * min(1, lambda1 / |a|_2) with the hardware reciprocal square root
+// (about 1 ulp; |a|^2 is held at or above the smallest normal float).
+__device__ inline float4 shrink_step(float4 h, float gx, float gy, float gz, float gt, float sigma,
+                                     float lambda1)
+{
+    const float ax = fmaf(sigma, gx, h.x);
+    const float ay = fmaf(sigma, gy, h.y);
+    const float az = fmaf(sigma, gz, h.z);
+    const float at = fmaf(sigma, gt, h.w);
+    const float n2 = fmaf(at, at, fmaf(az, az, fmaf(ay, ay, ax * ax)));
+    const float sc = lambda1 <= 0.f
+                         ? 0.f
+                         : fminf(1.f, lambda1 * __builtin_amdgcn_rsqf(fmaxf(n2, 1.17549435e-38f)));
+    return make_float4(ax * sc, ay * sc, az * sc, at * sc);
+}
+
+// Backward-difference divergence of one voxel and frame from the dual's
+// components at the voxel (xc, yc, zc, tc) and at its lower neighbours (xp,
+// yp, zp, tp); absent terms are passed as 0 (the boundary rows of div =
+// -grad^T); the z pair only counts when the volume has more than one slice.
+__device__ inline float div_step(float xc, float xp, float yc, float yp, bool zax, float zc,
+                                 float zp, float tc, float tp, float lambda2)
+{
+    float d = xc - xp;
+    d += yc - yp;
+    if (zax) d += zc - zp;
+    return fmaf(lambda2, tc - tp, d);
+}
+
+// Primal step and extrapolation of one coefficient: sdiv = (S^T div h2)_k.
+__device__ inline void primal_step(float fo, float adj, float sdiv, float tau, float cinv,
+                                   float theta, int accel, float &fnw, float &fx)
+{
+    fnw = fmaf(tau, sdiv, fmaf(-tau, adj, fo));
+    if (accel) {
+        fnw *= cinv;
+        fx = fmaf(theta, fnw - fo, fnw);
+    } else {
+        fx = fmaf(2.f, fnw, -fo);
+    }
+}
+
 // Cooperative copy of voxels [v0, v0 + nv) x K floats from global
 // (contiguous) to LDS rows of stride KS.
 template <int KT>
@@ -163,16 +210,15 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
                 // h2 of this voxel is read and written once here and next read
                 // after the back-projection has streamed through L2: streaming
                 // (non-temporal) accesses leave L2 to the frames' neighbour reads
-                const float ax = fmaf(sigma, gx, __builtin_nontemporal_load(pm));
-                const float ay = fmaf(sigma, gy, __builtin_nontemporal_load(pm + plane));
-                const float az = fmaf(sigma, gz, __builtin_nontemporal_load(pm + 2 * plane));
-                const float at = fmaf(sigma, gt, __builtin_nontemporal_load(pm + 3 * plane));
-                const float nrm = sqrtf(ax * ax + ay * ay + az * az + at * at);
-                const float sc = lambda1 <= 0.f ? 0.f : (nrm > lambda1 ? lambda1 / nrm : 1.f);
-                __builtin_nontemporal_store(ax * sc, pm);
-                __builtin_nontemporal_store(ay * sc, pm + plane);
-                __builtin_nontemporal_store(az * sc, pm + 2 * plane);
-                __builtin_nontemporal_store(at * sc, pm + 3 * plane);
+                const float4 h = make_float4(__builtin_nontemporal_load(pm),
+                                             __builtin_nontemporal_load(pm + plane),
+                                             __builtin_nontemporal_load(pm + 2 * plane),
+                                             __builtin_nontemporal_load(pm + 3 * plane));
+                const float4 a = shrink_step(h, gx, gy, gz, gt, sigma, lambda1);
+                __builtin_nontemporal_store(a.x, pm);
+                __builtin_nontemporal_store(a.y, pm + plane);
+                __builtin_nontemporal_store(a.z, pm + 2 * plane);
+                __builtin_nontemporal_store(a.w, pm + 3 * plane);
             }
             F0 = F1;
         }
@@ -231,13 +277,12 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
             float tprev = 0.f;
             for (int m = 0; m < Nt; ++m) {
                 const float *pm = pz + (size_t)m * 4 * plane;
-                float d = (q < N - 1 ? pm[0] : 0.f) - (q > 0 ? pm[-1] : 0.f);
-                d += (r < N - 1 ? pm[plane] : 0.f) - (r > 0 ? pm[plane - N] : 0.f);
-                if (Nz > 1)
-                    d += ((int)z < Nz - 1 ? pm[2 * plane] : 0.f) -
-                         (z > 0 ? *(pm + 2 * plane - (size_t)Nt * 4 * plane) : 0.f);
                 const float tcur = m < Nt - 1 ? pm[3 * plane] : 0.f;
-                d += lambda2 * (tcur - tprev);
+                const float d = div_step(
+                    q < N - 1 ? pm[0] : 0.f, q > 0 ? pm[-1] : 0.f,
+                    r < N - 1 ? pm[plane] : 0.f, r > 0 ? pm[plane - N] : 0.f, Nz > 1,
+                    (int)z < Nz - 1 ? pm[2 * plane] : 0.f,
+                    z > 0 ? *(pm + 2 * plane - (size_t)Nt * 4 * plane) : 0.f, tcur, tprev, lambda2);
                 tprev = tcur;
                 const float *Sm = sS + m * KT;
 #pragma unroll
@@ -260,14 +305,9 @@ __global__ __launch_bounds__(NT) void k_div(const float *__restrict__ pin,
                 float *slot = rows + (e / K) * KS + e % K;
                 // f, R*h1 and f~ are touched once per iteration: streaming accesses
                 const float fo = __builtin_nontemporal_load(fb + e);
-                float fnw = fo - tau * __builtin_nontemporal_load(ab + e) + tau * slot[0];
-                float fx;
-                if (accel) {
-                    fnw *= cinv;
-                    fx = fnw + theta * (fnw - fo);
-                } else {
-                    fx = 2.f * fnw - fo;
-                }
+                float fnw, fx;
+                primal_step(fo, __builtin_nontemporal_load(ab + e), slot[0], tau, cinv, theta, accel,
+                            fnw, fx);
                 const float dd = fnw - fo;
                 if (part) {
                     dn2 += (double)dd * dd;
