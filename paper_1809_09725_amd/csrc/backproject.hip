@@ -93,37 +93,31 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             s_D[tid] = (long long)llrint(sn * 34359738368.0);
         }
         __syncthreads();
-        if (VEC == 4) {
-            // thread: channel quad kq of window rows tid / NQ + RS i, row =
-            // c WMAX + w; c = row / WMAX from the float reciprocal of
-            // (row + 1/2), which lies at least 1/(2 WMAX) from an integer and
-            // carries a relative error of 2^-23, so it is exact for fewer
-            // than 2^22 rows (a window that fits the LDS has under 2^14);
-            // the products fit 24 bits (w < WMAX, K <= 64)
-            constexpr int NQ = KC / 4, RS = NT / NQ;
-            const int kq = tid % NQ;
-            const bool kin = k0 + 4 * kq < K;
-            const float invw = 1.f / (float)WMAX;
-            for (int row = tid / NQ; row < nca * WMAX; row += RS) {
-                const int c = (int)(((float)row + 0.5f) * invw);
-                const int w = row - __mul24(c, WMAX);
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (kin && w >= s_wb[c] && w < s_we[c])
-                    v = *(const float4 *)(gt + s_goff[c] + (__mul24(w, K) + 4 * kq));
-                *(float4 *)(win + __mul24(row, stride) + 4 * kq) = v;
-            }
-        } else {
-            // the same walk with one channel kk per thread (KC divides NT)
-            constexpr int RS = NT / KC;
-            const int kk = tid % KC;
-            const bool kin = k0 + kk < K;
-            const float invw = 1.f / (float)WMAX;
-            for (int row = tid / KC; row < nca * WMAX; row += RS) {
-                const int c = (int)(((float)row + 0.5f) * invw);
-                const int w = row - __mul24(c, WMAX);
-                float v = 0.f;
-                if (kin && w >= s_wb[c] && w < s_we[c]) v = gt[s_goff[c] + (__mul24(w, K) + kk)];
-                win[__mul24(row, stride) + kk] = v;
+        {
+            // NT / CA threads per class window (CA divides NT): thread j of
+            // class c stages channel group j % NG of window rows j / NG, j / NG
+            // + RS, ...; the class's bounds and offsets are read once per
+            // round and the products fit 24 bits (w < WMAX, K <= 64)
+            constexpr int NG = VEC == 4 ? KC / 4 : KC;   // channel groups per window row
+            const int tpc = NT / CA;
+            const int c = tid / tpc, j = tid - c * tpc;
+            const int q = j % NG, RS = tpc / NG;
+            const int kofs = VEC == 4 ? 4 * q : q;   // first channel of the group
+            if (c < nca) {
+                const int wb = s_wb[c], we = s_we[c];
+                const bool kin = k0 + kofs < K;
+                const float *src = gt + s_goff[c] + kofs;
+                float *dst = win + __mul24(c, WMAX) * stride + kofs;
+                for (int w = j / NG; w < WMAX; w += RS) {
+                    const bool in = kin && w >= wb && w < we;
+                    if constexpr (VEC == 4) {
+                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (in) v = *(const float4 *)(src + __mul24(w, K));
+                        *(float4 *)(dst + __mul24(w, stride)) = v;
+                    } else {
+                        dst[__mul24(w, stride)] = in ? src[__mul24(w, K)] : 0.f;
+                    }
+                }
             }
         }
         __syncthreads();
