@@ -82,7 +82,10 @@ typedef enum {
  * with RT_PREC_BF16MFMA it takes synthesise-first when K >= 2 Npi and
  * Npi <= 32, and project-first in FP32 otherwise; with RT_PREC_FP32 it is
  * project-first. */
-typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1, RT_FORM_AUTO = 2 } rt_form;
+/* (The _RT_*_I32 members make every 32-bit value a value of the enum type,
+ * so a caller's out-of-range argument reaches the library's check and its
+ * RT_E_ARG without undefined behaviour in the C++ that reads it.) */
+typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1, RT_FORM_AUTO = 2, _RT_FORM_I32 = 0x7fffffff } rt_form;
 
 /* RT_PREC_FP32: every product in FP32.  RT_PREC_BF16MFMA: the basis
  * contraction sum_k Phi f_k (and its transpose) in BF16 on the matrix cores
@@ -92,7 +95,7 @@ typedef enum { RT_FORM_PF = 0, RT_FORM_SF = 1, RT_FORM_AUTO = 2 } rt_form;
  * BF16 copy of the volume it last projected ([Nz][N][N][K rounded up to 16]);
  * rt_forward converts its input into it, a job refreshes it in the primal
  * update. */
-typedef enum { RT_PREC_FP32 = 0, RT_PREC_BF16MFMA = 1 } rt_prec;
+typedef enum { RT_PREC_FP32 = 0, RT_PREC_BF16MFMA = 1, _RT_PREC_I32 = 0x7fffffff } rt_prec;
 
 typedef struct rt_plan rt_plan;
 
@@ -172,7 +175,7 @@ int shrink(const rt_plan *plan, float *p, float lambda1, void *stream);
  *   theta_n = 1 / sqrt(1 + 2 mu tau_n),  f~ = f+ + theta_n (f+ - f),
  *   tau_{n+1} = theta_n tau_n,  sigma_{n+1} = sigma_n / theta_n.
  * With mu = 0 both variants are the plain loop. */
-typedef enum { RT_CP_PLAIN = 0, RT_CP_ACCEL = 1 } rt_cp_variant;
+typedef enum { RT_CP_PLAIN = 0, RT_CP_ACCEL = 1, _RT_CP_I32 = 0x7fffffff } rt_cp_variant;
 
 typedef struct {
     double lambda1, lambda2, tol, tau, sigma;

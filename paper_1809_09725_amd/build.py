@@ -1,6 +1,12 @@
 """Build librt4d.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-Usage: python -m paper_1809_09725_amd.build [--jobs N]
+Usage: python -m paper_1809_09725_amd.build [--jobs N] [--sanitize]
+
+--sanitize also writes _build/sanitize/librt4d.so: the host sources (plan,
+ABI, solver, timing, out-of-core driver) built with AddressSanitizer and
+UndefinedBehaviorSanitizer (host code only: each -fsanitize= follows
+-Xarch_host), linked with the regular device objects.  Load it in a process
+with the clang ASan runtime preloaded and RT4D_LIBRARY pointing at it.
 """
 from __future__ import annotations
 
@@ -56,7 +62,53 @@ def build(jobs: int = 6, verbose: bool = True) -> str:
     return LIB
 
 
+SANITIZE_DIR = os.path.join(ROOT, "_build", "sanitize")
+SANITIZE_LIB = os.path.join(SANITIZE_DIR, "librt4d.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+
+
+def asan_runtime() -> str | None:
+    """The clang ASan runtime that a sanitized library needs preloaded."""
+    import glob
+    hits = glob.glob("/opt/rocm*/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+    return sorted(hits)[-1] if hits else None
+
+
+def build_sanitized(jobs: int = 6) -> str:
+    """The host sources with ASan + UBSan, linked with build()'s device
+    objects (built first if any is missing)."""
+    if not all(os.path.exists(os.path.join(BUILD, s + ".o")) for s in SOURCES):
+        build(jobs, verbose=False)
+    os.makedirs(SANITIZE_DIR, exist_ok=True)
+    host = [s for s in SOURCES if s.endswith(".cpp")]
+
+    def one(src: str) -> str:
+        obj = os.path.join(SANITIZE_DIR, src + ".o")
+        flags = [f for f in COMMON if f != "-O3"]
+        cmd = [HIPCC, "-ffp-contract=off", *SANITIZE_FLAGS, *flags, "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, host))
+    dev = [os.path.join(BUILD, s + ".o") for s in SOURCES if not s.endswith(".cpp")]
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libasan", "-o", SANITIZE_LIB, *objs, *dev]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{r.stderr[-4000:]}")
+    return SANITIZE_LIB
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
-    build(ap.parse_args().jobs)
+    ap.add_argument("--sanitize", action="store_true")
+    a = ap.parse_args()
+    build(a.jobs)
+    if a.sanitize:
+        print(f"built {build_sanitized(a.jobs)}")

@@ -19,7 +19,9 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librt4d.so")
+# RT4D_LIBRARY names another build of the same library (the host-sanitizer
+# build that `python -m paper_1809_09725_amd.build --sanitize` writes)
+LIB_PATH = os.environ.get("RT4D_LIBRARY") or os.path.join(_HERE, "librt4d.so")
 
 RT_OK, RT_E_ARG, RT_E_SHAPE, RT_E_HIP, RT_E_OOM, RT_E_NONFINITE = 0, -1, -2, -3, -4, -5
 RT_FORM_PF, RT_FORM_SF, RT_FORM_AUTO = 0, 1, 2
