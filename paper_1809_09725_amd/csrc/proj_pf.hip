@@ -247,17 +247,8 @@ __global__ __launch_bounds__(NTH) void k_project(
             pf.store(buf, N, ex);
         }
     };
-    stage_load();
-    stage_store(lines);
-    __syncthreads();
-
-    for (int l = 0; l < N; ++l) {
-        const bool more = l + 1 < N;
-        if (more) {
-            src += lstep;
-            stage_load();
-        }
-        const float *line = lines + (nbuf == 2 ? (l & 1) * bufsz : 0);
+    // the taps of every ray on one staged line
+    auto line_taps = [&](const float *line) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int q0 = (int)(U[j] >> 32);
@@ -296,6 +287,67 @@ __global__ __launch_bounds__(NTH) void k_project(
             if constexpr (TL) taps(blk[TL ? j : 0]);
             else taps(acc[j]);
         }
+    };
+
+    if constexpr (EXACT) {
+        // Loads run two lines ahead of the taps (a line's loads have two
+        // lines' taps to arrive; one line was too short at one workgroup per
+        // CU): two register sets, A and B, alternate over line pairs, and the
+        // two LDS buffers alternate as before.  At the taps of line l, line
+        // l+1 waits in registers and line l+2 is being loaded.
+        static_assert(!TL, "the unmasked staging is planned for N = 512, without block sums");
+        constexpr int NL = 512;
+        constexpr int bsz = (NL + 2 * G0) * stride;
+        float4 ya, yb;
+        auto ldA = [&](int ln) {
+            const float *q = src + (size_t)ln * lstep;
+            xa = *(const float4 *)(q + ex.off);
+            xb = *(const float4 *)(q + ex.off + ex.inc);
+        };
+        auto ldB = [&](int ln) {
+            const float *q = src + (size_t)ln * lstep;
+            ya = *(const float4 *)(q + ex.off);
+            yb = *(const float4 *)(q + ex.off + ex.inc);
+        };
+        auto stA = [&](float *buf) {
+            *(float4 *)(buf + ex.dst) = xa;
+            *(float4 *)(buf + ex.dst + ex.dinc) = xb;
+        };
+        auto stB = [&](float *buf) {
+            *(float4 *)(buf + ex.dst) = ya;
+            *(float4 *)(buf + ex.dst + ex.dinc) = yb;
+        };
+        ldA(0);
+        stA(lines);
+        ldB(1);
+        __syncthreads();
+        // The loads and stores are unconditional (past the end they repeat
+        // the last line into a buffer no one reads again): a conditional
+        // store would let the compiler sink its loads next to it, and a
+        // conditional load would make it wait for every load in flight.
+        for (int l = 0; l < NL; l += 2) {
+            // line l in buffer 0, line l+1 in B
+            ldA(min(l + 2, NL - 1));
+            line_taps(lines);
+            stB(lines + bsz);
+            __syncthreads();
+            // line l+1 in buffer 1, line l+2 in A
+            ldB(min(l + 3, NL - 1));
+            line_taps(lines + bsz);
+            stA(lines);
+            __syncthreads();
+        }
+    } else {
+    stage_load();
+    stage_store(lines);
+    __syncthreads();
+    for (int l = 0; l < N; ++l) {
+        const bool more = l + 1 < N;
+        if (more) {
+            src += lstep;
+            stage_load();
+        }
+        line_taps(lines + (nbuf == 2 ? (l & 1) * bufsz : 0));
         if constexpr (TL) {
             if ((l + 1) % LB == 0 || !more) {
 #pragma unroll
@@ -312,6 +364,7 @@ __global__ __launch_bounds__(NTH) void k_project(
         if (nbuf == 1) __syncthreads();
         if (more) stage_store(lines + (nbuf == 2 ? ((l + 1) & 1) * bufsz : 0));
         __syncthreads();
+    }
     }
 
     double d2 = 0.0;
