@@ -204,18 +204,27 @@ __global__ __launch_bounds__(ST) void k_project_sf(
         if (nsteps > 0) load_step(0);
     }
 
+    // Ray positions in 32.32 fixed point, as in the plain projector: u at
+    // line lbeg from FP64 once, then one exact integer add of the slope per
+    // line (the position carries the rounding of its start and of l s alone,
+    // below 2^-32 (1 + l)).  A ray outside the tile sits at -1e6.
+    long long U[R], Sl[R];
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+        const double u0 = fmin(fmax(fma((double)lbeg - hN, slope[rho], base[rho]), -1.0e6), 1.0e6);
+        U[rho] = (long long)llrint(u0 * 4294967296.0);
+        Sl[rho] = (long long)llrint(slope[rho] * 4294967296.0);
+    }
     int q0[R];
     float w0[R], w1[R];
     for (int st = 0; st < nsteps; ++st) {
-        const int l = lbeg + st / nch, c0 = (st % nch) * PCH;
-        if (c0 == 0) {   // ray positions on line l
-            const double lc = (double)l - hN;
+        const int c0 = (st % nch) * PCH;
+        if (c0 == 0) {   // ray positions on this step's line
 #pragma unroll
             for (int rho = 0; rho < R; ++rho) {
-                const double u = fma(lc, slope[rho], base[rho]);
-                const double fl = floor(u);
-                const int q = (int)fl;
-                const float frc = (float)(u - fl);
+                const int q = (int)(U[rho] >> 32);
+                const float frc = (float)(unsigned)U[rho] * 2.3283064365386963e-10f;
+                U[rho] += Sl[rho];
                 const bool in = (unsigned)(q + 1) <= (unsigned)N;
                 q0[rho] = in ? q : -(1 << 28);
                 w1[rho] = in ? frc * invc[rho] : 0.f;
