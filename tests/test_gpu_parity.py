@@ -64,6 +64,8 @@ SHAPES = [
     rt4d.Geom(N=96, Nz=2, Ns=100, Ntheta=2 * 60, Npi=2, K=16, Nt=2),   # 1024 threads x 2 rays
     rt4d.Geom(N=150, Nz=2, Ns=192, Ntheta=2 * 90, Npi=2, K=16, Nt=2),  # ... lanes reordered in blocks of 64 bins
     rt4d.Geom(N=1024, Nz=1, Ns=96, Ntheta=2 * 8, Npi=2, K=8, Nt=2),    # 8 rays per thread
+    rt4d.Geom(N=600, Nz=1, Ns=700, Ntheta=2 * 8, Npi=2, K=16, Nt=2),   # 16 channels in two chunks, block sums
+    rt4d.Geom(N=1024, Nz=1, Ns=1024, Ntheta=2 * 4, Npi=2, K=16, Nt=2), # ... over 1024 positions and bins
     rt4d.Geom(N=2048, Nz=1, Ns=64, Ntheta=2 * 4, Npi=2, K=16, Nt=2),   # ... and one line buffer
     rt4d.Geom(N=1, Nz=1, Ns=1, Ntheta=1, Npi=1, K=1, Nt=1),            # one ray
 ]
