@@ -170,34 +170,40 @@ template <int MODE>
 __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float lambda2,
                                              float sigma, float lambda1, float *__restrict__ p,
                                              double *__restrict__ part, int N, int Nz, int Nt,
-                                             int zbeg, int zend)
+                                             int zbeg, int zend, int carry)
 {
     __shared__ double sh[NT / 64];
+    // carry != 0: sFn[m][thread] holds the frames of slice z+1 at the
+    // thread's pixel, read as z-neighbours, so the next slice of the work item
+    // takes its own frames from LDS instead of reading them again
+    extern __shared__ float sFn[];   // [Nt][NT] when carry
     const size_t plane = (size_t)N * N;
     const size_t nitem = plane * ((zend - zbeg + ZC - 1) / ZC);
     double tvs = 0.0;
-    // a work item is one (row, column) over ZC consecutive slices, so the
-    // z-neighbour frames one slice reads are still in L2 when the next one
-    // reads them as its own
+    float *cf = sFn + threadIdx.x;
+    // a work item is one (row, column) over ZC consecutive slices
     for (size_t it = (size_t)blockIdx.x * NT + threadIdx.x; it < nitem; it += (size_t)gridDim.x * NT)
-    for (int z = zbeg + (int)(it / plane) * ZC, ze = min(zend, z + ZC); z < ze; ++z) {
+    for (int z0 = zbeg + (int)(it / plane) * ZC, z = z0, ze = min(zend, z + ZC); z < ze; ++z) {
         const size_t pv = it % plane;
         const int q = (int)(pv % N);
         const int r = (int)(pv / N);
         const bool hx = q < N - 1, hy = r < N - 1, hz = z < Nz - 1;
+        const bool own = carry && z > z0;   // this slice's frames are in LDS
         const float *Fz = F + (size_t)z * Nt * plane + pv;
         float *pz = (MODE != 2) ? p + (size_t)z * Nt * 4 * plane + pv : nullptr;
-        float F0 = Fz[0];
+        float F0 = own ? cf[0] : Fz[0];
         for (int m = 0; m < Nt; ++m) {
             const float *Fm = Fz + (size_t)m * plane;
             const float gx = hx ? Fm[1] - F0 : 0.f;
             const float gy = hy ? Fm[N] - F0 : 0.f;
-            const float gz = hz ? Fm[(size_t)Nt * plane] - F0 : 0.f;
+            const float Fzn = hz ? Fm[(size_t)Nt * plane] : 0.f;
+            const float gz = hz ? Fzn - F0 : 0.f;
             float gt = 0.f, F1 = 0.f;
             if (m < Nt - 1) {
-                F1 = Fm[plane];
+                F1 = own ? cf[(m + 1) * NT] : Fm[plane];
                 gt = lambda2 * (F1 - F0);
             }
+            if (carry) cf[m * NT] = Fzn;   // frame m of slice z+1 (entry m was last read above)
             if (part) tvs += sqrt((double)gx * gx + (double)gy * gy + (double)gz * gz + (double)gt * gt);
             if (MODE == 0) {
                 float *pm = pz + (size_t)m * 4 * plane;
@@ -392,6 +398,14 @@ int launch_frames(const Plan &p, const float *f, float *F, hipStream_t s)
     return RT_OK;
 }
 
+// LDS of the gradient's slice-to-slice carry: one float per frame and
+// thread, when it fits a modest budget (else the kernel reads again)
+static size_t carry_lds(const rt_geom &g)
+{
+    const size_t b = (size_t)g.Nt * NT * sizeof(float);
+    return b <= 32 * 1024 ? b : 0;
+}
+
 static int launch_grad_mode(const Plan &p, int mode, const char *name, const float *F, float *pout,
                             float sigma, float lambda1, float lambda2, double *part, hipStream_t s,
                             int zbeg = 0, int zend = -1)
@@ -400,13 +414,15 @@ static int launch_grad_mode(const Plan &p, int mode, const char *name, const flo
     if (zend <= zbeg) return RT_OK;
     const unsigned nb = voxel_blocks(p.g);
     const rt_geom &g = p.g;
+    const size_t lds = carry_lds(g);
+    const int carry = lds > 0;
     KTimer kt(name, s);
     if (mode == 0)
-        hipLaunchKernelGGL(k_grad<0>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
+        hipLaunchKernelGGL(k_grad<0>, dim3(nb), dim3(NT), lds, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend, carry);
     else if (mode == 1)
-        hipLaunchKernelGGL(k_grad<1>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
+        hipLaunchKernelGGL(k_grad<1>, dim3(nb), dim3(NT), lds, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend, carry);
     else
-        hipLaunchKernelGGL(k_grad<2>, dim3(nb), dim3(NT), 0, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend);
+        hipLaunchKernelGGL(k_grad<2>, dim3(nb), dim3(NT), lds, s, F, lambda2, sigma, lambda1, pout, part, g.N, g.Nz, g.Nt, zbeg, zend, carry);
     kt.stop();
     RT_HIP(hipGetLastError());
     return RT_OK;
