@@ -181,8 +181,10 @@ __global__ __launch_bounds__(NT) void k_grad(const float *__restrict__ F, float 
     const size_t nitem = plane * ((zend - zbeg + ZC - 1) / ZC);
     double tvs = 0.0;
     float *cf = sFn + threadIdx.x;
-    // a work item is one (row, column) over ZC consecutive slices
-    for (size_t it = (size_t)blockIdx.x * NT + threadIdx.x; it < nitem; it += (size_t)gridDim.x * NT)
+    // a work item is one (row, column) over ZC consecutive slices; the
+    // workgroups of a plane's rows y and y+1 share an XCD's L2 (xcd_remap)
+    const size_t lid = xcd_remap(blockIdx.x, gridDim.x);
+    for (size_t it = lid * NT + threadIdx.x; it < nitem; it += (size_t)gridDim.x * NT)
     for (int z0 = zbeg + (int)(it / plane) * ZC, z = z0, ze = min(zend, z + ZC); z < ze; ++z) {
         const size_t pv = it % plane;
         const int q = (int)(pv % N);
