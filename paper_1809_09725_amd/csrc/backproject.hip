@@ -38,7 +38,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
     __shared__ int s_wb[BP_MAXCA], s_we[BP_MAXCA];   // window rows [wb, we) hold bins 0..Ns-1
     __shared__ long long s_goff[BP_MAXCA];           // element offset of window row 0's bin in gt
     __shared__ float s_inv[BP_MAXCA];                     // 1/c, c = max(|cos|, |sin|)
-    __shared__ float s_ic01[BP_MAXCA], s_s2[BP_MAXCA];    // 1/c - 1/c^2 and 2^-32 / c^2
+    __shared__ float s_ic1[BP_MAXCA], s_s1[BP_MAXCA];     // 1 - 1/c and 2^-32 / c
     __shared__ double s_base[BP_MAXCA];                   // hS - (bin of window row 0)
     __shared__ long long s_D[BP_MAXCA];                   // 8 sin in 32.32 fixed point
     unsigned lid = xcd_remap(blockIdx.x, nblocks);
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             s_goff[tid] = (((long long)(a0 + tid) * Nz + z) * Ns + lo) * K + k0;
             const double ic = 1.0 / fmax(fabs(cs), fabs(sn));
             s_inv[tid] = (float)ic;
-            s_ic01[tid] = (float)ic - (float)(ic * ic);
-            s_s2[tid] = (float)(ic * ic) * 2.3283064365386963e-10f;
+            s_ic1[tid] = (float)(1.0 - ic);
+            s_s1[tid] = (float)ic * 2.3283064365386963e-10f;
             s_base[tid] = hS - (double)lo;
             s_D[tid] = (long long)llrint(sn * 34359738368.0);
         }
@@ -97,7 +97,9 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             // NT / CA threads per class window (CA divides NT): thread j of
             // class c stages channel group j % NG of window rows j / NG, j / NG
             // + RS, ...; the class's bounds and offsets are read once per
-            // round and the products fit 24 bits (w < WMAX, K <= 64)
+            // round and the products fit 24 bits (w < WMAX, K <= 64).  The
+            // window holds g~ / c, so that the weights below are c times the
+            // triangle weights, in [0, 1].
             constexpr int NG = VEC == 4 ? KC / 4 : KC;   // channel groups per window row
             const int tpc = NT / CA;
             const int c = tid / tpc, j = tid - c * tpc;
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
             const int kofs = VEC == 4 ? 4 * q : q;   // first channel of the group
             if (c < nca) {
                 const int wb = s_wb[c], we = s_we[c];
+                const float sc = s_inv[c];
                 const bool kin = k0 + kofs < K;
                 const float *src = gt + s_goff[c] + kofs;
                 float *dst = win + __mul24(c, WMAX) * stride + kofs;
@@ -113,9 +116,13 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
                     if constexpr (VEC == 4) {
                         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (in) v = *(const float4 *)(src + __mul24(w, K));
+                        v.x *= sc;
+                        v.y *= sc;
+                        v.z *= sc;
+                        v.w *= sc;
                         *(float4 *)(dst + __mul24(w, stride)) = v;
                     } else {
-                        dst[__mul24(w, stride)] = in ? src[__mul24(w, K)] : 0.f;
+                        dst[__mul24(w, stride)] = in ? src[__mul24(w, K)] * sc : 0.f;
                     }
                 }
             }
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
         __syncthreads();
         for (int c = 0; c < nca; ++c) {
             const double cs = ccos[a0 + c], sn = csin[a0 + c];
-            const float invc = s_inv[c], ic01 = s_ic01[c], s2 = s_s2[c];
+            const float ic1 = s_ic1[c], s1 = s_s1[c];
             // s_p minus the bin of the window's row 0, for the thread's first
             // row: at least 1 up to FP64 rounding (the window keeps a spare bin
             // below the tile's lowest position), so truncation is floor
@@ -143,10 +150,11 @@ __global__ __launch_bounds__(NT, 2) void k_backproject(
                 }
                 const unsigned row = (unsigned)(U >> 32);
                 const float fq = (float)(unsigned)U;   // the fraction in units of 2^-32
-                // triangle weights of the bins floor(u) and floor(u)+1,
-                // max(0, 1 - |s_b - s_p| / c) / c = max(0, 1/c - |s_b - s_p| / c^2)
-                const float w0 = fmaxf(0.f, fmaf(-fq, s2, invc));
-                const float w1 = fmaxf(0.f, fmaf(fq, s2, ic01));
+                // triangle weights of the bins floor(u) and floor(u)+1 times c
+                // (the window holds g~ / c), max(0, 1 - |s_b - s_p| / c), which
+                // is at most 1: one fma with the clamp to [0, 1] each
+                const float w0 = fminf(fmaxf(fmaf(-fq, s1, 1.f), 0.f), 1.f);
+                const float w1 = fminf(fmaxf(fmaf(fq, s1, ic1), 0.f), 1.f);
                 const float *t0 = win + __umul24(row, stride);
 #pragma unroll
                 for (int k = 0; k < KC; k += 4) {

@@ -28,12 +28,12 @@ namespace {
 constexpr int FT = 512;   // threads of a projection workgroup (8 wave64)
 constexpr int G0 = LINE_GUARD;   // zero guard positions at each end of a staged line
 
-// clamp to [lo, hi] in one v_med3_i32 (the compiler forms it only for
-// constant bounds)
-__device__ inline int clamp_i32(int x, int lo, int hi)
+// clamp to [0, hi] in one v_med3_i32 (the compiler forms it only for
+// constant bounds); hi is uniform and stays in an SGPR
+__device__ inline int clamp0_i32(int x, int hi)
 {
     int r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
     return r;
 }
 
@@ -167,10 +167,11 @@ __global__ __launch_bounds__(NTH) void k_project(
 
     // Ray positions along the lines in 32.32 fixed point: u(l) = u(0) + l s,
     // stepped by an exact integer add per line, so u(l) carries the rounding
-    // of u(0) and of l s alone (below 2^-32 (1 + l) positions).  Its integer
-    // part is the left tap, its fraction the interpolation weight.  A ray
-    // outside the tile has 1/c = 0; a position before the line or past it is
-    // clamped into the zero guard slots.
+    // of u(0) and of l s alone (below 2^-32 (1 + l) positions).  U holds
+    // u + G0, so its integer part is the left tap's LDS slot and its fraction
+    // the interpolation weight.  A ray outside the tile has 1/c = 0; a
+    // position before the line or past it is clamped into the zero guard
+    // slots.
     long long U[PPT], S[PPT];
     float invc[PPT], sfr[PPT];
 #pragma unroll
@@ -193,7 +194,8 @@ __global__ __launch_bounds__(NTH) void k_project(
             }
         }
         const double u0 = fmin(fmax(fma(-hN, slope, base), -1.0e6), 1.0e6);   // line 0
-        U[j] = (long long)llrint(u0 * 4294967296.0);
+        U[j] = (long long)llrint(u0 * 4294967296.0) + ((long long)G0 << 32);
+        asm volatile("" : "+v"(U[j]));   // keeps the offset inside U (else it is re-added per line)
         S[j] = (long long)llrint(slope * 4294967296.0);
         sfr[j] = invc[j] * 2.3283064365386963e-10f;   // fraction bits -> weight: 2^-32 / c
     }
@@ -251,12 +253,12 @@ __global__ __launch_bounds__(NTH) void k_project(
     auto line_taps = [&](const float *line) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const int q0 = (int)(U[j] >> 32);
+            const int q0 = (int)(U[j] >> 32);   // slot of the left tap, before the clamp
             const float fr = (float)(unsigned)U[j];
             U[j] += S[j];
             const float w1 = fr * sfr[j];
             const float w0 = invc[j] - w1;
-            const float *t0 = line + __umul24((unsigned)(clamp_i32(q0, -G0, N) + G0), (unsigned)stride);
+            const float *t0 = line + __umul24((unsigned)clamp0_i32(q0, N + G0), (unsigned)stride);
             // the taps of this ray into s (the ray's sums or its block sums);
             // its FMAs finish before the next ray's tap loads are issued:
             // hoisting the loads of all rays needs 32 VGPRs per ray and spills
