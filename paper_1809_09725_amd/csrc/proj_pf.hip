@@ -256,6 +256,7 @@ __global__ __launch_bounds__(NTH) void k_project(
             const int q0 = (int)(U[j] >> 32);   // slot of the left tap, before the clamp
             const float fr = (float)(unsigned)U[j];
             U[j] += S[j];
+            asm volatile("" : "+v"(U[j]));   // one 64-bit add per line, not U(0) + l s rebuilt
             const float w1 = fr * sfr[j];
             const float w0 = invc[j] - w1;
             const float *t0 = line + __umul24((unsigned)clamp0_i32(q0, N + G0), (unsigned)stride);
@@ -300,24 +301,31 @@ __global__ __launch_bounds__(NTH) void k_project(
         static_assert(!TL, "the unmasked staging is planned for N = 512, without block sums");
         constexpr int NL = 512;
         constexpr int bsz = (NL + 2 * G0) * stride;
-        float4 ya, yb;
+        // Buffer loads over the slice: the thread's two offsets stay in
+        // VGPRs and the line's offset goes in an SGPR, so a load costs no
+        // vector address arithmetic.  Every offset is inside the slice
+        // (line < NL, element offsets as in LinePrefetch::exact).
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)src, (short)0, (int)(((size_t)N * N * K - k0) * sizeof(float)), 0x00020000);
+        const int vo0 = ex.off * (int)sizeof(float), vo1 = (ex.off + ex.inc) * (int)sizeof(float);
+        const int lsb = (int)(lstep * sizeof(float));   // bytes per line, < 2^31 / NL
+        v4u ra, rb, rc, rd;
         auto ldA = [&](int ln) {
-            const float *q = src + (size_t)ln * lstep;
-            xa = *(const float4 *)(q + ex.off);
-            xb = *(const float4 *)(q + ex.off + ex.inc);
+            ra = __builtin_amdgcn_raw_buffer_load_b128(rs, vo0, ln * lsb, 0);
+            rb = __builtin_amdgcn_raw_buffer_load_b128(rs, vo1, ln * lsb, 0);
         };
         auto ldB = [&](int ln) {
-            const float *q = src + (size_t)ln * lstep;
-            ya = *(const float4 *)(q + ex.off);
-            yb = *(const float4 *)(q + ex.off + ex.inc);
+            rc = __builtin_amdgcn_raw_buffer_load_b128(rs, vo0, ln * lsb, 0);
+            rd = __builtin_amdgcn_raw_buffer_load_b128(rs, vo1, ln * lsb, 0);
         };
         auto stA = [&](float *buf) {
-            *(float4 *)(buf + ex.dst) = xa;
-            *(float4 *)(buf + ex.dst + ex.dinc) = xb;
+            *(v4u *)(buf + ex.dst) = ra;
+            *(v4u *)(buf + ex.dst + ex.dinc) = rb;
         };
         auto stB = [&](float *buf) {
-            *(float4 *)(buf + ex.dst) = ya;
-            *(float4 *)(buf + ex.dst + ex.dinc) = yb;
+            *(v4u *)(buf + ex.dst) = rc;
+            *(v4u *)(buf + ex.dst + ex.dinc) = rd;
         };
         ldA(0);
         stA(lines);
