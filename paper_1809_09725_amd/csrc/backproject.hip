@@ -27,8 +27,11 @@ __device__ inline int bp_col(int tid) { return 8 * (tid >> 6) + (tid & 7); }
 __device__ inline int bp_row(int tid) { return (tid >> 3) & 7; }
 constexpr int BP_MAXCA = 16;  // classes staged per round, at most
 
+// Four workgroups per CU: the bound holds the 16-channel kernel to 128
+// VGPRs (4 waves per SIMD, no spills) instead of 158 (3 waves), which
+// measured 5% faster at 512^2 and 2% at 1024^2
 template <int KC, int VEC>
-__global__ __launch_bounds__(NT, 2) void k_backproject(
+__global__ __launch_bounds__(NT, 4) void k_backproject(
     const float *__restrict__ gt, float *__restrict__ out, const double *__restrict__ ccos,
     const double *__restrict__ csin, int N, int Nz, int Ns, int K, int n0, int nkc, int ntq,
     int ntr, int CA, int WMAX, unsigned nblocks)
